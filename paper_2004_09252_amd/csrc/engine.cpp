@@ -1,0 +1,1248 @@
+// Host engine behind the C ABI of include/memshield.h.
+//
+// Responsibilities (MemShield, section 4.4 "GPU encryption" and section 3):
+//   * the key store: a device key table, keys entering through a pinned
+//     staging buffer that is wiped at once, never leaving the GPU again;
+//   * argument validation, so that a bad size or pointer becomes an error
+//     code instead of a GPU fault;
+//   * plain launches (one run of pages, one key) and fused batched launches
+//     (many requests, many keys, one persistent launch, replayed from a
+//     captured hipGraph);
+//   * the serving path: many host threads submit requests (the paper's
+//     multiple-producer queue); one scheduler thread admits them into fused
+//     launches as batch slots and the in-flight byte budget free up, so
+//     batches overlap on the device, and marks tickets complete.
+#include <hip/hip_runtime.h>
+#include <sys/random.h>
+#include <time.h>
+#include <unistd.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "memshield.h"
+#include "ms_kernels.h"
+#include "tune_cache.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr uint32_t kMaxKeysLimit = 65536;
+
+inline bool hip_ok(hipError_t e) { return e == hipSuccess; }
+
+// Wipe that the compiler may not drop.
+void secure_zero(void* p, size_t n) {
+  volatile uint8_t* v = static_cast<volatile uint8_t*>(p);
+  for (size_t i = 0; i < n; ++i) v[i] = 0;
+  std::atomic_signal_fence(std::memory_order_seq_cst);
+}
+
+bool ranges_overlap(uintptr_t a, uint64_t na, uintptr_t b, uint64_t nb) {
+  return a < b + nb && b < a + na;
+}
+
+struct Tuning {
+  uint32_t ppw = 4;
+  uint32_t unroll = 1;
+  uint32_t waves_per_cu = 32;
+  double us = 0.0;
+};
+
+// One reusable batch buffer: pinned host descriptors, their device copy, a
+// completion event and the graphs captured for this buffer.
+struct BatchSlot {
+  uint8_t* host = nullptr;    // pinned, DevBatchHdr + DevReq[capacity]
+  uint8_t* dev = nullptr;     // device copy read by the kernel
+  size_t capacity = 0;        // requests
+  hipEvent_t done = nullptr;  // recorded after the launch that used it
+  bool used = false;
+  // graphs keyed by (unroll, ppw, grid)
+  struct G {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy = nullptr;
+  };
+  std::map<uint64_t, G> graphs;
+};
+
+// A request the scheduler owns.
+struct Pending {
+  ms_request req;
+  uint32_t ticket_slot;
+  bool prefetch;
+};
+
+struct TicketSlot {
+  std::atomic<uint32_t> gen{0};
+  std::atomic<int32_t> state{0};  // 0 pending, 1 done, <0 ms_status
+};
+
+struct InflightBatch {
+  int slot;
+  int stream;
+  std::vector<uint32_t> tickets;
+  std::vector<uint32_t> key_slots;
+  uint64_t bytes;
+};
+
+}  // namespace
+
+struct ms_ctx {
+  int device = 0;
+  ms_config cfg{};
+  hipStream_t stream = nullptr;
+  int cu_count = 0;
+  std::string arch;
+
+  // ---- key store ----
+  std::mutex key_mu;
+  uint32_t* d_keys = nullptr;       // max_keys x 8 words
+  uint8_t* h_staging = nullptr;     // pinned, 32 bytes
+  std::vector<uint32_t> key_gen;    // current generation per slot
+  std::vector<uint8_t> key_live;
+  std::unique_ptr<std::atomic<int64_t>[]> key_refs;  // submitted, unfinished
+
+  // ---- batched launches from ms_process_batch ----
+  std::mutex batch_mu;
+  std::vector<BatchSlot> sync_slots;
+  size_t sync_next = 0;
+
+  // ---- tuning ----
+  std::mutex tune_mu;
+  std::map<uint32_t, Tuning> tuned;  // log2 bucket -> tuning
+  bool forced = false;
+  Tuning forced_tuning;
+
+  // ---- serving ----
+  std::vector<TicketSlot> tickets;
+  std::mutex ticket_mu;
+  std::vector<uint32_t> ticket_free;
+  std::atomic<uint64_t> outstanding{0};
+
+  std::mutex q_mu;  // submission queue (multiple producers)
+  std::condition_variable q_cv;
+  std::deque<Pending> demand_q;
+  std::deque<Pending> prefetch_q;
+  std::atomic<bool> stop{false};
+  std::thread scheduler;
+
+  std::vector<BatchSlot> serve_slots;
+  std::vector<hipStream_t> serve_streams;
+  std::vector<int> serve_free;
+  std::deque<InflightBatch> inflight;
+  uint64_t inflight_bytes = 0;  // scheduler thread only (mirrored in stats)
+
+  std::atomic<int32_t> sticky_error{0};
+
+  // ---- stats ----
+  std::atomic<uint64_t> st_submitted{0}, st_completed{0}, st_eagain{0},
+      st_batches{0}, st_pages{0}, st_pf_issued{0}, st_pf_dropped{0},
+      st_cancelled{0}, st_inflight_bytes{0}, st_max_inflight{0},
+      st_max_batch{0};
+};
+
+namespace {
+
+ms_status dev_err(ms_ctx* c, hipError_t e) {
+  if (e == hipSuccess) return MS_OK;
+  if (c) c->sticky_error.store(MS_EDEVICE);
+  return MS_EDEVICE;
+}
+
+ms_status check_sticky(ms_ctx* c) {
+  return c->sticky_error.load() ? MS_EDEVICE : MS_OK;
+}
+
+// A device range [p, p+bytes) must lie inside one device allocation.
+ms_status check_device_range(ms_ctx* c, const void* p, uint64_t bytes,
+                             uint64_t align) {
+  if (!p) return MS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(p) % align) return MS_EINVAL;
+  if (!c->cfg.validate_pointers) return MS_OK;
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return MS_EINVAL;
+  }
+  if (attr.type != hipMemoryTypeDevice) return MS_EINVAL;
+  if (attr.device != c->device) return MS_EINVAL;
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return MS_EINVAL;
+  }
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+  const uintptr_t q = reinterpret_cast<uintptr_t>(p);
+  if (q < b || bytes > size || q - b > size - bytes) return MS_EINVAL;
+  return MS_OK;
+}
+
+bool resolve_key(ms_ctx* c, ms_key k, uint32_t* slot) {
+  if (k == 0) return false;
+  const uint32_t s = (uint32_t)(k & 0xffffffffu);
+  const uint32_t g = (uint32_t)(k >> 32);
+  if (s == 0 || s > c->cfg.max_keys) return false;
+  std::lock_guard<std::mutex> lk(c->key_mu);
+  if (!c->key_live[s - 1] || c->key_gen[s - 1] != g) return false;
+  *slot = s - 1;
+  return true;
+}
+
+ms_status check_nonce(ms_ctx* c, const ms_nonce* n, uint64_t n_pages) {
+  if (!n) return MS_EINVAL;
+  if (n->kind == MS_NONCE_ARRAY) {
+    if (n_pages > (UINT64_MAX / 12)) return MS_EINVAL;
+    return check_device_range(c, n->array, n_pages * 12u, 4);
+  }
+  if (n->kind == MS_NONCE_LINEAR) return MS_OK;
+  return MS_EINVAL;
+}
+
+// Validate one request (pages, pointers, overlap, key, nonce).
+ms_status check_request(ms_ctx* c, const ms_request& r, uint32_t* slot,
+                        bool allow_empty) {
+  if (r.priority != 0 || r.flags != 0) return MS_EINVAL;
+  if (r.op != MS_ENCRYPT && r.op != MS_DECRYPT) return MS_EINVAL;
+  if (r.n_pages == 0) {
+    if (!allow_empty) return MS_EINVAL;
+  } else {
+    if (r.n_pages > (UINT64_MAX / MS_PAGE_SIZE)) return MS_EINVAL;
+    const uint64_t bytes = r.n_pages * MS_PAGE_SIZE;
+    ms_status st = check_device_range(c, r.src, bytes, 16);
+    if (st) return st;
+    st = check_device_range(c, r.dst, bytes, 16);
+    if (st) return st;
+    const uintptr_t s = reinterpret_cast<uintptr_t>(r.src);
+    const uintptr_t d = reinterpret_cast<uintptr_t>(r.dst);
+    if (s != d && ranges_overlap(s, bytes, d, bytes)) return MS_EINVAL;
+    st = check_nonce(c, &r.nonce, r.n_pages);
+    if (st) return st;
+  }
+  if (!resolve_key(c, r.key, slot)) return MS_ENOKEY;
+  return MS_OK;
+}
+
+uint32_t bucket_of(uint64_t n_pages) {
+  uint32_t b = 0;
+  while ((1ull << b) < n_pages && b < 63) ++b;
+  return b;
+}
+
+Tuning default_tuning(uint64_t n_pages) {
+  Tuning t;
+  t.unroll = 1;
+  t.ppw = n_pages >= (1u << 16) ? 8 : (n_pages >= 4096 ? 4 : 1);
+  t.waves_per_cu = 32;
+  return t;
+}
+
+Tuning tuning_for(ms_ctx* c, uint64_t n_pages) {
+  std::lock_guard<std::mutex> lk(c->tune_mu);
+  if (c->forced) return c->forced_tuning;
+  auto it = c->tuned.find(bucket_of(n_pages));
+  if (it != c->tuned.end()) return it->second;
+  return default_tuning(n_pages);
+}
+
+uint32_t grid_blocks_for(ms_ctx* c, const Tuning& t, uint64_t total_pages) {
+  const uint64_t items = (total_pages + t.ppw - 1) / t.ppw;
+  const uint64_t max_waves = (uint64_t)c->cu_count * t.waves_per_cu;
+  uint64_t waves = std::min<uint64_t>(std::max<uint64_t>(items, 1), max_waves);
+  uint64_t blocks = (waves + ms::kWavesPerBlock - 1) / ms::kWavesPerBlock;
+  return (uint32_t)std::max<uint64_t>(blocks, 1);
+}
+
+ms_status alloc_slot(BatchSlot& s, size_t capacity) {
+  const size_t bytes =
+      sizeof(ms::DevBatchHdr) + capacity * sizeof(ms::DevReq);
+  if (!hip_ok(hipHostMalloc(reinterpret_cast<void**>(&s.host), bytes,
+                            hipHostMallocDefault)))
+    return MS_ENOMEM;
+  if (!hip_ok(hipMalloc(reinterpret_cast<void**>(&s.dev), bytes)))
+    return MS_ENOMEM;
+  if (!hip_ok(hipEventCreateWithFlags(&s.done, hipEventDisableTiming)))
+    return MS_EDEVICE;
+  std::memset(s.host, 0, bytes);
+  s.capacity = capacity;
+  return MS_OK;
+}
+
+void free_slot(BatchSlot& s) {
+  for (auto& kv : s.graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+  s.graphs.clear();
+  if (s.done) (void)hipEventDestroy(s.done);
+  if (s.dev) (void)hipFree(s.dev);
+  if (s.host) (void)hipHostFree(s.host);
+  s = BatchSlot();
+}
+
+// Lay the requests out in the slot's pinned buffer. Empty requests are
+// skipped.  Returns the number of bytes to copy (0 when there is no work).
+size_t fill_slot(BatchSlot& s, const ms_request* const* reqs,
+                 const uint32_t* key_slots, size_t n, uint64_t* total_out) {
+  auto* hdr = reinterpret_cast<ms::DevBatchHdr*>(s.host);
+  auto* dr = reinterpret_cast<ms::DevReq*>(hdr + 1);
+  uint64_t total = 0;
+  uint32_t m = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const ms_request& r = *reqs[i];
+    if (r.n_pages == 0) continue;
+    ms::DevReq& d = dr[m++];
+    d.src = reinterpret_cast<uint64_t>(r.src);
+    d.dst = reinterpret_cast<uint64_t>(r.dst);
+    if (r.nonce.kind == MS_NONCE_ARRAY) {
+      d.kind = ms::kNonceArray;
+      d.nonce = reinterpret_cast<uint64_t>(r.nonce.array);
+      d.stride = 0;
+      d.tag = 0;
+    } else {
+      d.kind = ms::kNonceLinear;
+      d.nonce = r.nonce.base;
+      d.stride = r.nonce.stride;
+      d.tag = r.nonce.tag;
+    }
+    d.page_begin = total;
+    total += r.n_pages;
+    d.page_end = total;
+    d.key_slot = key_slots[i];
+    d.pad = 0;
+  }
+  hdr->total_pages = total;
+  hdr->n_req = m;
+  *total_out = total;
+  if (m == 0) return 0;
+  return sizeof(ms::DevBatchHdr) + (size_t)m * sizeof(ms::DevReq);
+}
+
+// Capture [copy descriptors H2D] -> [fused kernel] for this slot and tiling.
+ms_status get_graph(ms_ctx* c, BatchSlot& s, const Tuning& t, uint32_t grid,
+                    BatchSlot::G** out) {
+  const uint64_t key = ((uint64_t)t.unroll << 56) ^ ((uint64_t)t.ppw << 32) ^
+                       (uint64_t)grid;
+  auto it = s.graphs.find(key);
+  if (it != s.graphs.end()) {
+    *out = &it->second;
+    return MS_OK;
+  }
+  BatchSlot::G g;
+  if (!hip_ok(hipGraphCreate(&g.graph, 0))) return MS_EDEVICE;
+  const size_t full =
+      sizeof(ms::DevBatchHdr) + s.capacity * sizeof(ms::DevReq);
+  hipError_t e = hipGraphAddMemcpyNode1D(&g.copy, g.graph, nullptr, 0, s.dev,
+                                         s.host, full, hipMemcpyHostToDevice);
+  if (!hip_ok(e)) {
+    (void)hipGraphDestroy(g.graph);
+    return dev_err(c, e);
+  }
+  const ms::DevBatchHdr* hdr = reinterpret_cast<const ms::DevBatchHdr*>(s.dev);
+  const uint32_t* keys = c->d_keys;
+  uint32_t ppw = t.ppw;
+  void* args[] = {(void*)&hdr, (void*)&keys, (void*)&ppw};
+  hipKernelNodeParams kp;
+  std::memset(&kp, 0, sizeof(kp));
+  kp.func = const_cast<void*>(ms::batch_kernel_fn(t.unroll, (int)c->cfg.rounds));
+  kp.gridDim = dim3(grid);
+  kp.blockDim = dim3(ms::kBlockThreads);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  hipGraphNode_t kn;
+  e = hipGraphAddKernelNode(&kn, g.graph, &g.copy, 1, &kp);
+  if (!hip_ok(e)) {
+    (void)hipGraphDestroy(g.graph);
+    return dev_err(c, e);
+  }
+  e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+  if (!hip_ok(e)) {
+    (void)hipGraphDestroy(g.graph);
+    return dev_err(c, e);
+  }
+  auto ins = s.graphs.emplace(key, g);
+  *out = &ins.first->second;
+  return MS_OK;
+}
+
+// Issue a filled slot on `stream`: graph replay or copy + launch.
+ms_status issue_slot(ms_ctx* c, BatchSlot& s, size_t copy_bytes,
+                     uint64_t total, hipStream_t stream, bool use_graph) {
+  const Tuning t = tuning_for(c, total);
+  const uint32_t grid = grid_blocks_for(c, t, total);
+  hipError_t e;
+  if (use_graph) {
+    BatchSlot::G* g = nullptr;
+    ms_status st = get_graph(c, s, t, grid, &g);
+    if (st) return st;
+    e = hipGraphExecMemcpyNodeSetParams1D(g->exec, g->copy, s.dev, s.host,
+                                          copy_bytes, hipMemcpyHostToDevice);
+    if (!hip_ok(e)) return dev_err(c, e);
+    e = hipGraphLaunch(g->exec, stream);
+    if (!hip_ok(e)) return dev_err(c, e);
+  } else {
+    e = hipMemcpyAsync(s.dev, s.host, copy_bytes, hipMemcpyHostToDevice,
+                       stream);
+    if (!hip_ok(e)) return dev_err(c, e);
+    e = ms::launch_batch(reinterpret_cast<const ms::DevBatchHdr*>(s.dev),
+                         c->d_keys, t.ppw, t.unroll, grid, (int)c->cfg.rounds,
+                         stream);
+    if (!hip_ok(e)) return dev_err(c, e);
+  }
+  e = hipEventRecord(s.done, stream);
+  if (!hip_ok(e)) return dev_err(c, e);
+  s.used = true;
+  return MS_OK;
+}
+
+// ------------------------------------------------------------ scheduler ---
+
+void finish_batch(ms_ctx* c, InflightBatch& b, int32_t state) {
+  for (uint32_t ks : b.key_slots) c->key_refs[ks].fetch_sub(1);
+  {
+    std::lock_guard<std::mutex> lk(c->ticket_mu);
+    for (uint32_t t : b.tickets) {
+      c->tickets[t].state.store(state, std::memory_order_release);
+      c->ticket_free.push_back(t);
+    }
+  }
+  c->outstanding.fetch_sub(b.tickets.size());
+  c->st_completed.fetch_add(b.tickets.size());
+  c->inflight_bytes -= b.bytes;
+  c->st_inflight_bytes.store(c->inflight_bytes);
+  c->serve_free.push_back(b.slot);
+}
+
+void complete_ticket_now(ms_ctx* c, uint32_t t, int32_t state,
+                         uint32_t key_slot) {
+  c->key_refs[key_slot].fetch_sub(1);
+  {
+    std::lock_guard<std::mutex> lk(c->ticket_mu);
+    c->tickets[t].state.store(state, std::memory_order_release);
+    c->ticket_free.push_back(t);
+  }
+  c->outstanding.fetch_sub(1);
+}
+
+// Poll in-flight batches; returns true when any completed.
+bool reap(ms_ctx* c) {
+  bool any = false;
+  for (auto it = c->inflight.begin(); it != c->inflight.end();) {
+    hipError_t q = hipEventQuery(c->serve_slots[it->slot].done);
+    if (q == hipErrorNotReady) {
+      ++it;
+      continue;
+    }
+    int32_t state = 1;
+    if (q != hipSuccess) {
+      c->sticky_error.store(MS_EDEVICE);
+      state = MS_EDEVICE;
+    }
+    finish_batch(c, *it, state);
+    it = c->inflight.erase(it);
+    any = true;
+  }
+  return any;
+}
+
+// Form and launch one batch from the queues; returns false if nothing
+// could be launched.
+bool launch_one(ms_ctx* c) {
+  if (c->serve_free.empty()) return false;
+  std::vector<Pending> take;
+  const uint64_t cap = c->cfg.admission_cap_bytes;
+  uint64_t bytes = 0;
+  {
+    std::lock_guard<std::mutex> lk(c->q_mu);
+    const size_t maxn = c->cfg.max_batch_requests;
+    while (!c->demand_q.empty() && take.size() < maxn) {
+      const uint64_t b = c->demand_q.front().req.n_pages * MS_PAGE_SIZE;
+      if (c->inflight_bytes + bytes + b > cap) break;
+      bytes += b;
+      take.push_back(c->demand_q.front());
+      c->demand_q.pop_front();
+    }
+    // prefetch hints only ride along when no demand request is waiting
+    if (c->demand_q.empty()) {
+      while (!c->prefetch_q.empty() && take.size() < maxn) {
+        const uint64_t b = c->prefetch_q.front().req.n_pages * MS_PAGE_SIZE;
+        if (c->inflight_bytes + bytes + b > cap) break;
+        bytes += b;
+        take.push_back(c->prefetch_q.front());
+        c->prefetch_q.pop_front();
+      }
+    }
+  }
+  if (take.empty()) return false;
+  const int slot = c->serve_free.back();
+  c->serve_free.pop_back();
+  const int stream_i = slot % (int)c->serve_streams.size();
+  BatchSlot& s = c->serve_slots[slot];
+  std::vector<const ms_request*> rp(take.size());
+  std::vector<uint32_t> ks(take.size());
+  InflightBatch b;
+  b.slot = slot;
+  b.stream = stream_i;
+  b.bytes = bytes;
+  uint64_t n_pf = 0;
+  for (size_t i = 0; i < take.size(); ++i) {
+    rp[i] = &take[i].req;
+    // the key slot was resolved and referenced at submit time
+    ks[i] = (uint32_t)(take[i].req.key & 0xffffffffu) - 1;
+    b.tickets.push_back(take[i].ticket_slot);
+    b.key_slots.push_back(ks[i]);
+    n_pf += take[i].prefetch ? 1 : 0;
+  }
+  uint64_t total = 0;
+  const size_t copy = fill_slot(s, rp.data(), ks.data(), take.size(), &total);
+  c->inflight_bytes += bytes;
+  c->st_inflight_bytes.store(c->inflight_bytes);
+  if (c->inflight_bytes > c->st_max_inflight.load())
+    c->st_max_inflight.store(c->inflight_bytes);
+  if (take.size() > c->st_max_batch.load()) c->st_max_batch.store(take.size());
+  c->st_batches.fetch_add(1);
+  c->st_pages.fetch_add(total);
+  c->st_pf_issued.fetch_add(n_pf);
+  ms_status st = MS_OK;
+  if (copy) st = issue_slot(c, s, copy, total, c->serve_streams[stream_i],
+                            false);
+  else if (!hip_ok(hipEventRecord(s.done, c->serve_streams[stream_i])))
+    st = MS_EDEVICE;
+  if (st != MS_OK) {
+    finish_batch(c, b, st);
+    return true;
+  }
+  c->inflight.push_back(std::move(b));
+  return true;
+}
+
+void scheduler_main(ms_ctx* c) {
+  (void)hipSetDevice(c->device);
+  auto last_work = Clock::now();
+  for (;;) {
+    bool did = reap(c);
+    while (launch_one(c)) did = true;
+    if (did) {
+      last_work = Clock::now();
+      continue;
+    }
+    bool queues_empty;
+    {
+      std::lock_guard<std::mutex> lk(c->q_mu);
+      queues_empty = c->demand_q.empty() && c->prefetch_q.empty();
+    }
+    if (c->stop.load() && queues_empty && c->inflight.empty()) break;
+    if (!c->inflight.empty()) {
+      // work on the device: poll its completion closely
+      std::this_thread::yield();
+      continue;
+    }
+    if (!queues_empty) {
+      // blocked by admission with nothing in flight cannot happen (a single
+      // request never exceeds the cap); just retry
+      std::this_thread::yield();
+      continue;
+    }
+    // idle: spin briefly for low latency, then sleep until a submission
+    if (Clock::now() - last_work < std::chrono::microseconds(200)) {
+      std::this_thread::yield();
+      continue;
+    }
+    std::unique_lock<std::mutex> lk(c->q_mu);
+    c->q_cv.wait_for(lk, std::chrono::milliseconds(2), [c] {
+      return c->stop.load() || !c->demand_q.empty() || !c->prefetch_q.empty();
+    });
+  }
+}
+
+ms_status alloc_tickets(ms_ctx* c, size_t n, uint32_t* out) {
+  std::lock_guard<std::mutex> lk(c->ticket_mu);
+  if (c->ticket_free.size() < n) return MS_EAGAIN;
+  for (size_t i = 0; i < n; ++i) {
+    out[i] = c->ticket_free.back();
+    c->ticket_free.pop_back();
+    TicketSlot& t = c->tickets[out[i]];
+    t.gen.fetch_add(1);
+    t.state.store(0);
+  }
+  return MS_OK;
+}
+
+ms_ticket make_ticket(ms_ctx* c, uint32_t slot) {
+  return ((uint64_t)c->tickets[slot].gen.load() << 32) | (uint64_t)(slot + 1);
+}
+
+ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
+                  ms_ticket* tickets_out, bool prefetch) {
+  if (!c) return MS_EINVAL;
+  if (c->stop.load()) return MS_ECLOSED;
+  if (n == 0) return MS_OK;
+  if (!reqs) return MS_EINVAL;
+  ms_status st = check_sticky(c);
+  if (st) return st;
+  std::vector<uint32_t> ks(n);
+  for (size_t i = 0; i < n; ++i) {
+    st = check_request(c, reqs[i], &ks[i], false);
+    if (st) return st;
+    if (reqs[i].n_pages * MS_PAGE_SIZE > c->cfg.admission_cap_bytes)
+      return MS_EINVAL;
+  }
+  const uint64_t prev = c->outstanding.fetch_add(n);
+  if (prev + n > c->cfg.queue_depth) {
+    c->outstanding.fetch_sub(n);
+    if (prefetch) {
+      c->st_pf_dropped.fetch_add(n);
+      if (tickets_out)
+        for (size_t i = 0; i < n; ++i) tickets_out[i] = 0;
+      return MS_OK;
+    }
+    c->st_eagain.fetch_add(1);
+    return MS_EAGAIN;
+  }
+  if (prefetch) {
+    std::lock_guard<std::mutex> lk(c->q_mu);
+    if (c->prefetch_q.size() + n > c->cfg.prefetch_depth) {
+      c->outstanding.fetch_sub(n);
+      c->st_pf_dropped.fetch_add(n);
+      if (tickets_out)
+        for (size_t i = 0; i < n; ++i) tickets_out[i] = 0;
+      return MS_OK;
+    }
+  }
+  std::vector<uint32_t> ts(n);
+  st = alloc_tickets(c, n, ts.data());
+  if (st) {
+    c->outstanding.fetch_sub(n);
+    if (prefetch) {
+      c->st_pf_dropped.fetch_add(n);
+      if (tickets_out)
+        for (size_t i = 0; i < n; ++i) tickets_out[i] = 0;
+      return MS_OK;
+    }
+    c->st_eagain.fetch_add(1);
+    return st;
+  }
+  // Take a reference on every key under the key lock, re-checking that each
+  // handle is still live, so that ms_key_destroy cannot slip in between.
+  {
+    std::lock_guard<std::mutex> lk(c->key_mu);
+    for (size_t i = 0; i < n; ++i) {
+      const uint32_t g = (uint32_t)(reqs[i].key >> 32);
+      if (!c->key_live[ks[i]] || c->key_gen[ks[i]] != g) {
+        st = MS_ENOKEY;
+        break;
+      }
+    }
+    if (!st)
+      for (size_t i = 0; i < n; ++i) c->key_refs[ks[i]].fetch_add(1);
+  }
+  if (st) {
+    std::lock_guard<std::mutex> lk(c->ticket_mu);
+    for (size_t i = 0; i < n; ++i) c->ticket_free.push_back(ts[i]);
+    c->outstanding.fetch_sub(n);
+    return st;
+  }
+  {
+    std::lock_guard<std::mutex> lk(c->q_mu);
+    for (size_t i = 0; i < n; ++i) {
+      Pending p;
+      p.req = reqs[i];
+      // store the resolved slot in the low word, generation unchanged
+      p.req.key = (reqs[i].key & 0xffffffff00000000ull) | (ks[i] + 1);
+      p.ticket_slot = ts[i];
+      p.prefetch = prefetch;
+      (prefetch ? c->prefetch_q : c->demand_q).push_back(p);
+    }
+  }
+  c->q_cv.notify_one();
+  if (!prefetch) c->st_submitted.fetch_add(n);
+  if (tickets_out)
+    for (size_t i = 0; i < n; ++i) tickets_out[i] = make_ticket(c, ts[i]);
+  return MS_OK;
+}
+
+ms_status plain_call(ms_ctx* c, ms_key key, const void* src, void* dst,
+                     uint64_t n_pages, const ms_nonce* nonce, void* stream) {
+  if (!c) return MS_EINVAL;
+  ms_status st = check_sticky(c);
+  if (st) return st;
+  if (n_pages == 0) return MS_OK;
+  ms_request r;
+  std::memset(&r, 0, sizeof(r));
+  r.op = MS_ENCRYPT;
+  r.key = key;
+  r.src = src;
+  r.dst = dst;
+  r.n_pages = n_pages;
+  if (!nonce) return MS_EINVAL;
+  r.nonce = *nonce;
+  uint32_t slot = 0;
+  st = check_request(c, r, &slot, false);
+  if (st) return st;
+  ms::PlainArgs a;
+  a.keys = c->d_keys;
+  a.src = static_cast<const uint8_t*>(src);
+  a.dst = static_cast<uint8_t*>(dst);
+  a.nonce_array = reinterpret_cast<const uint32_t*>(nonce->array);
+  a.nonce_base = nonce->base;
+  a.nonce_stride = nonce->stride;
+  a.first_page = 0;
+  a.n_pages = n_pages;
+  a.key_slot = slot;
+  a.nonce_tag = nonce->tag;
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  const uint32_t kind =
+      nonce->kind == MS_NONCE_ARRAY ? ms::kNonceArray : ms::kNonceLinear;
+  return dev_err(c, ms::launch_plain(a, kind, (int)c->cfg.rounds, s));
+}
+
+ms_status install_key(ms_ctx* c, ms_key* out) {
+  // caller holds key_mu and has filled h_staging
+  uint32_t slot = UINT32_MAX;
+  for (uint32_t i = 0; i < c->cfg.max_keys; ++i)
+    if (!c->key_live[i]) {
+      slot = i;
+      break;
+    }
+  if (slot == UINT32_MAX) {
+    secure_zero(c->h_staging, MS_KEY_BYTES);
+    return MS_ENOMEM;
+  }
+  hipError_t e = hipMemcpyAsync(c->d_keys + (size_t)slot * 8, c->h_staging,
+                                MS_KEY_BYTES, hipMemcpyHostToDevice, c->stream);
+  if (hip_ok(e)) e = hipStreamSynchronize(c->stream);
+  secure_zero(c->h_staging, MS_KEY_BYTES);
+  if (!hip_ok(e)) return dev_err(c, e);
+  c->key_live[slot] = 1;
+  uint32_t g = ++c->key_gen[slot];
+  if (g == 0) g = ++c->key_gen[slot];
+  *out = ((uint64_t)g << 32) | (uint64_t)(slot + 1);
+  return MS_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI ===
+
+extern "C" {
+
+void ms_config_default(ms_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->max_keys = 64;
+  cfg->rounds = 20;
+  cfg->queue_depth = 65536;
+  cfg->max_batch_requests = 1024;
+  cfg->admission_cap_bytes = 8ull << 30;
+  cfg->inflight_batches = 4;
+  cfg->prefetch_depth = 4096;
+  cfg->validate_pointers = 1;
+  cfg->use_graphs = 1;
+}
+
+const char* ms_status_str(ms_status st) {
+  switch (st) {
+    case MS_OK: return "ok";
+    case MS_EINVAL: return "invalid argument";
+    case MS_ENOKEY: return "unknown or stale key handle";
+    case MS_ENOMEM: return "out of memory or key table full";
+    case MS_EAGAIN: return "queue full or admission cap reached";
+    case MS_EBUSY: return "key in use by requests in flight";
+    case MS_EDEVICE: return "GPU or HIP runtime error";
+    case MS_ECLOSED: return "context shutting down";
+    case MS_ETIMEDOUT: return "timed out";
+    case MS_ENOTSUP: return "not supported";
+    case MS_ECANCELED: return "cancelled";
+  }
+  return "unknown status";
+}
+
+ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
+  if (!out) return MS_EINVAL;
+  ms_config cfg;
+  if (cfg_in) cfg = *cfg_in; else ms_config_default(&cfg);
+  if (cfg.max_keys == 0 || cfg.max_keys > kMaxKeysLimit) return MS_EINVAL;
+  if (cfg.rounds != 20 && cfg.rounds != 12 && cfg.rounds != 8)
+    return MS_EINVAL;
+  if (cfg.queue_depth == 0 || (cfg.queue_depth & (cfg.queue_depth - 1)) ||
+      cfg.queue_depth > (1u << 24))
+    return MS_EINVAL;
+  if (cfg.max_batch_requests == 0 || cfg.max_batch_requests > (1u << 20))
+    return MS_EINVAL;
+  if (cfg.inflight_batches == 0 || cfg.inflight_batches > 64)
+    return MS_EINVAL;
+  if (cfg.admission_cap_bytes < MS_PAGE_SIZE) return MS_EINVAL;
+  int ndev = 0;
+  if (!hip_ok(hipGetDeviceCount(&ndev))) return MS_EDEVICE;
+  if (hip_device < 0 || hip_device >= ndev) return MS_EINVAL;
+  if (!hip_ok(hipSetDevice(hip_device))) return MS_EDEVICE;
+
+  ms_ctx* c = new (std::nothrow) ms_ctx();
+  if (!c) return MS_ENOMEM;
+  c->device = hip_device;
+  c->cfg = cfg;
+  hipDeviceProp_t prop;
+  if (!hip_ok(hipGetDeviceProperties(&prop, hip_device))) {
+    delete c;
+    return MS_EDEVICE;
+  }
+  c->cu_count = prop.multiProcessorCount;
+  c->arch = prop.gcnArchName;
+  ms_status st = MS_OK;
+  const size_t key_bytes = (size_t)cfg.max_keys * MS_KEY_BYTES;
+  if (!hip_ok(hipStreamCreate(&c->stream))) st = MS_EDEVICE;
+  if (!st && !hip_ok(hipMalloc(reinterpret_cast<void**>(&c->d_keys),
+                               key_bytes)))
+    st = MS_ENOMEM;
+  if (!st && !hip_ok(hipMemset(c->d_keys, 0, key_bytes))) st = MS_EDEVICE;
+  if (!st && !hip_ok(hipHostMalloc(reinterpret_cast<void**>(&c->h_staging),
+                                   MS_KEY_BYTES, hipHostMallocDefault)))
+    st = MS_ENOMEM;
+  if (!st) {
+    secure_zero(c->h_staging, MS_KEY_BYTES);
+    c->key_gen.assign(cfg.max_keys, 0);
+    c->key_live.assign(cfg.max_keys, 0);
+    c->key_refs.reset(new std::atomic<int64_t>[cfg.max_keys]);
+    for (uint32_t i = 0; i < cfg.max_keys; ++i) c->key_refs[i].store(0);
+    c->tickets = std::vector<TicketSlot>(cfg.queue_depth);
+    c->ticket_free.reserve(cfg.queue_depth);
+    for (uint32_t i = cfg.queue_depth; i-- > 0;) c->ticket_free.push_back(i);
+    c->sync_slots.resize(4);
+    for (auto& s : c->sync_slots)
+      if (!st) st = alloc_slot(s, cfg.max_batch_requests);
+    c->serve_slots.resize(cfg.inflight_batches);
+    for (auto& s : c->serve_slots)
+      if (!st) st = alloc_slot(s, cfg.max_batch_requests);
+    c->serve_streams.resize(cfg.inflight_batches, nullptr);
+    for (auto& s : c->serve_streams)
+      if (!st && !hip_ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)))
+        st = MS_EDEVICE;
+    for (int i = (int)cfg.inflight_batches; i-- > 0;)
+      c->serve_free.push_back(i);
+  }
+  if (!st) {
+    ms_tune_cache_load(c->arch.c_str(), c->cu_count,
+                       [c](uint32_t bucket, uint32_t ppw, uint32_t unroll,
+                           uint32_t wpc, double us) {
+                         Tuning t;
+                         t.ppw = ppw;
+                         t.unroll = unroll;
+                         t.waves_per_cu = wpc;
+                         t.us = us;
+                         c->tuned[bucket] = t;
+                       });
+    try {
+      c->scheduler = std::thread(scheduler_main, c);
+    } catch (...) {
+      st = MS_ENOMEM;
+    }
+  }
+  if (st) {
+    ms_shutdown(c);
+    return st;
+  }
+  *out = c;
+  return MS_OK;
+}
+
+ms_status ms_shutdown(ms_ctx* c) {
+  if (!c) return MS_OK;
+  (void)hipSetDevice(c->device);
+  c->stop.store(true);
+  c->q_cv.notify_all();
+  if (c->scheduler.joinable()) c->scheduler.join();
+  (void)hipDeviceSynchronize();
+  if (c->d_keys) {
+    (void)hipMemset(c->d_keys, 0, (size_t)c->cfg.max_keys * MS_KEY_BYTES);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(c->d_keys);
+  }
+  if (c->h_staging) {
+    secure_zero(c->h_staging, MS_KEY_BYTES);
+    (void)hipHostFree(c->h_staging);
+  }
+  for (auto& s : c->sync_slots) free_slot(s);
+  for (auto& s : c->serve_slots) free_slot(s);
+  for (auto& s : c->serve_streams)
+    if (s) (void)hipStreamDestroy(s);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return MS_OK;
+}
+
+ms_status ms_key_load(ms_ctx* c, const uint8_t key[32], ms_key* out) {
+  if (!c || !key || !out) return MS_EINVAL;
+  ms_status st = check_sticky(c);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(c->key_mu);
+  std::memcpy(c->h_staging, key, MS_KEY_BYTES);
+  return install_key(c, out);
+}
+
+ms_status ms_key_generate(ms_ctx* c, ms_key* out) {
+  if (!c || !out) return MS_EINVAL;
+  ms_status st = check_sticky(c);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(c->key_mu);
+  size_t got = 0;
+  while (got < MS_KEY_BYTES) {
+    ssize_t r = getrandom(c->h_staging + got, MS_KEY_BYTES - got, 0);
+    if (r < 0) {
+      secure_zero(c->h_staging, MS_KEY_BYTES);
+      return MS_EDEVICE;
+    }
+    got += (size_t)r;
+  }
+  return install_key(c, out);
+}
+
+ms_status ms_key_destroy(ms_ctx* c, ms_key key) {
+  if (!c) return MS_EINVAL;
+  uint32_t slot = 0;
+  if (!resolve_key(c, key, &slot)) return MS_ENOKEY;
+  std::lock_guard<std::mutex> lk(c->key_mu);
+  if (!c->key_live[slot] || c->key_gen[slot] != (uint32_t)(key >> 32))
+    return MS_ENOKEY;
+  if (c->key_refs[slot].load() != 0) return MS_EBUSY;
+  // stream-ordered launches on any stream may still read the slot
+  hipError_t e = hipDeviceSynchronize();
+  if (hip_ok(e)) e = hipMemset(c->d_keys + (size_t)slot * 8, 0, MS_KEY_BYTES);
+  if (hip_ok(e)) e = hipDeviceSynchronize();
+  c->key_live[slot] = 0;
+  return dev_err(c, e);
+}
+
+ms_status ms_encrypt_pages(ms_ctx* c, ms_key key, const void* src, void* dst,
+                           uint64_t n_pages, const ms_nonce* nonce,
+                           void* stream) {
+  return plain_call(c, key, src, dst, n_pages, nonce, stream);
+}
+
+ms_status ms_decrypt_pages(ms_ctx* c, ms_key key, const void* src, void* dst,
+                           uint64_t n_pages, const ms_nonce* nonce,
+                           void* stream) {
+  return plain_call(c, key, src, dst, n_pages, nonce, stream);
+}
+
+ms_status ms_process_batch(ms_ctx* c, const ms_request* reqs, size_t n,
+                           void* stream) {
+  if (!c) return MS_EINVAL;
+  ms_status st = check_sticky(c);
+  if (st) return st;
+  if (n == 0) return MS_OK;
+  if (!reqs || n > c->cfg.max_batch_requests) return MS_EINVAL;
+  std::vector<uint32_t> ks(n);
+  std::vector<const ms_request*> rp(n);
+  for (size_t i = 0; i < n; ++i) {
+    st = check_request(c, reqs[i], &ks[i], true);
+    if (st) return st;
+    rp[i] = &reqs[i];
+  }
+  // destinations must not overlap each other, nor any source other than
+  // their own request's (in place is allowed)
+  {
+    std::vector<std::pair<uintptr_t, uint64_t>> d;
+    for (size_t i = 0; i < n; ++i)
+      if (reqs[i].n_pages)
+        d.emplace_back(reinterpret_cast<uintptr_t>(reqs[i].dst),
+                       reqs[i].n_pages * MS_PAGE_SIZE);
+    std::sort(d.begin(), d.end());
+    for (size_t i = 1; i < d.size(); ++i)
+      if (d[i - 1].first + d[i - 1].second > d[i].first) return MS_EINVAL;
+    for (size_t i = 0; i < n; ++i) {
+      if (!reqs[i].n_pages) continue;
+      const uintptr_t s = reinterpret_cast<uintptr_t>(reqs[i].src);
+      const uintptr_t own = reinterpret_cast<uintptr_t>(reqs[i].dst);
+      const uint64_t nb = reqs[i].n_pages * MS_PAGE_SIZE;
+      // destinations are disjoint and sorted, so their ends are sorted too:
+      // walk back from the last one that starts before this source ends
+      auto it = std::lower_bound(d.begin(), d.end(),
+                                 std::make_pair(s + nb, (uint64_t)0));
+      while (it != d.begin()) {
+        --it;
+        if (it->first + it->second <= s) break;
+        if (it->first == own && own == s) continue;  // in place
+        return MS_EINVAL;
+      }
+    }
+  }
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  std::lock_guard<std::mutex> lk(c->batch_mu);
+  BatchSlot& slot = c->sync_slots[c->sync_next];
+  c->sync_next = (c->sync_next + 1) % c->sync_slots.size();
+  if (slot.used && !hip_ok(hipEventSynchronize(slot.done)))
+    return dev_err(c, hipErrorUnknown);
+  uint64_t total = 0;
+  const size_t copy = fill_slot(slot, rp.data(), ks.data(), n, &total);
+  if (!copy) return MS_OK;
+  return issue_slot(c, slot, copy, total, s, c->cfg.use_graphs != 0);
+}
+
+ms_status ms_submit(ms_ctx* c, const ms_request* reqs, size_t n,
+                    ms_ticket* tickets_out) {
+  if (n && !tickets_out) return MS_EINVAL;
+  return enqueue(c, reqs, n, tickets_out, false);
+}
+
+ms_status ms_prefetch_hint(ms_ctx* c, const ms_request* reqs, size_t n,
+                           ms_ticket* tickets_out) {
+  return enqueue(c, reqs, n, tickets_out, true);
+}
+
+ms_status ms_poll(ms_ctx* c, const ms_ticket* t, size_t n, int32_t* done,
+                  uint64_t timeout_ns) {
+  if (!c || (n && (!t || !done))) return MS_EINVAL;
+  for (size_t i = 0; i < n; ++i) {
+    const uint32_t s = (uint32_t)(t[i] & 0xffffffffu);
+    if (t[i] != 0 && (s == 0 || s > c->tickets.size())) return MS_EINVAL;
+  }
+  const auto deadline = Clock::now() + std::chrono::nanoseconds(timeout_ns);
+  for (;;) {
+    size_t pending = 0;
+    for (size_t i = 0; i < n; ++i) {
+      if (t[i] == 0) {  // a dropped prefetch hint
+        done[i] = MS_ECANCELED;
+        continue;
+      }
+      const uint32_t s = (uint32_t)(t[i] & 0xffffffffu) - 1;
+      const uint32_t g = (uint32_t)(t[i] >> 32);
+      TicketSlot& ts = c->tickets[s];
+      const int32_t state = ts.state.load(std::memory_order_acquire);
+      const uint32_t cur = ts.gen.load(std::memory_order_acquire);
+      if (cur != g) {
+        done[i] = 1;  // slot reused: this ticket completed long ago
+      } else {
+        done[i] = state;
+        if (state == 0) ++pending;
+      }
+    }
+    if (pending == 0) return MS_OK;
+    if (Clock::now() >= deadline) return MS_ETIMEDOUT;
+    std::this_thread::yield();
+  }
+}
+
+ms_status ms_cancel_client(ms_ctx* c, uint32_t client, uint64_t* n_out) {
+  if (!c) return MS_EINVAL;
+  std::vector<Pending> gone;
+  {
+    std::lock_guard<std::mutex> lk(c->q_mu);
+    for (auto* q : {&c->demand_q, &c->prefetch_q}) {
+      std::deque<Pending> keep;
+      for (auto& p : *q) {
+        if (p.req.client == client) gone.push_back(p);
+        else keep.push_back(p);
+      }
+      q->swap(keep);
+    }
+  }
+  for (auto& p : gone)
+    complete_ticket_now(c, p.ticket_slot, MS_ECANCELED,
+                        (uint32_t)(p.req.key & 0xffffffffu) - 1);
+  c->st_cancelled.fetch_add(gone.size());
+  if (n_out) *n_out = gone.size();
+  return MS_OK;
+}
+
+ms_status ms_drain(ms_ctx* c, uint64_t timeout_ns) {
+  if (!c) return MS_EINVAL;
+  const auto deadline = Clock::now() + std::chrono::nanoseconds(timeout_ns);
+  while (c->outstanding.load() != 0) {
+    if (Clock::now() >= deadline) return MS_ETIMEDOUT;
+    std::this_thread::yield();
+  }
+  return check_sticky(c);
+}
+
+ms_status ms_get_tuning(ms_ctx* c, uint64_t n_pages, ms_tuning* out) {
+  if (!c || !out) return MS_EINVAL;
+  Tuning t = tuning_for(c, n_pages);
+  std::memset(out, 0, sizeof(*out));
+  out->pages_per_wave = t.ppw;
+  out->unroll = t.unroll;
+  out->waves_per_cu = t.waves_per_cu;
+  out->us_per_launch = t.us;
+  return MS_OK;
+}
+
+ms_status ms_set_tuning(ms_ctx* c, const ms_tuning* t) {
+  if (!c) return MS_EINVAL;
+  std::lock_guard<std::mutex> lk(c->tune_mu);
+  if (!t) {
+    c->forced = false;
+    return MS_OK;
+  }
+  if (t->pages_per_wave == 0 || t->pages_per_wave > 4096 ||
+      (t->unroll != 1 && t->unroll != 2) || t->waves_per_cu == 0 ||
+      t->waves_per_cu > 256)
+    return MS_EINVAL;
+  c->forced = true;
+  c->forced_tuning.ppw = t->pages_per_wave;
+  c->forced_tuning.unroll = t->unroll;
+  c->forced_tuning.waves_per_cu = t->waves_per_cu;
+  c->forced_tuning.us = 0;
+  return MS_OK;
+}
+
+ms_status ms_autotune(ms_ctx* c, uint64_t n_pages, ms_tuning* out) {
+  if (!c || n_pages == 0 || n_pages > (1ull << 22)) return MS_EINVAL;
+  ms_status st = check_sticky(c);
+  if (st) return st;
+  // scratch batch: 64 requests of mixed sizes summing to n_pages
+  const uint64_t bytes = n_pages * MS_PAGE_SIZE;
+  uint8_t* buf = nullptr;
+  if (!hip_ok(hipMalloc(reinterpret_cast<void**>(&buf), bytes)))
+    return MS_ENOMEM;
+  BatchSlot slot;
+  st = alloc_slot(slot, 64);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!st && (!hip_ok(hipEventCreate(&e0)) || !hip_ok(hipEventCreate(&e1))))
+    st = MS_EDEVICE;
+  ms_key k = 0;
+  if (!st) st = ms_key_generate(c, &k);
+  Tuning best;
+  best.us = 1e30;
+  if (!st) {
+    uint32_t slot_idx = (uint32_t)(k & 0xffffffffu) - 1;
+    std::vector<ms_request> reqs;
+    const uint64_t nreq = std::min<uint64_t>(64, n_pages);
+    uint64_t off = 0;
+    for (uint64_t i = 0; i < nreq; ++i) {
+      // uneven split: request i gets a share growing with i
+      uint64_t share = (i + 1 == nreq) ? n_pages - off
+                                       : std::max<uint64_t>(1, (n_pages * 2 * (i + 1)) / (nreq * (nreq + 1)));
+      if (off + share > n_pages - (nreq - 1 - i)) share = n_pages - (nreq - 1 - i) - off;
+      ms_request r;
+      std::memset(&r, 0, sizeof(r));
+      r.key = k;
+      r.src = buf + off * MS_PAGE_SIZE;
+      r.dst = buf + off * MS_PAGE_SIZE;
+      r.n_pages = share;
+      r.nonce.kind = MS_NONCE_LINEAR;
+      r.nonce.base = off;
+      r.nonce.stride = 1;
+      reqs.push_back(r);
+      off += share;
+    }
+    std::vector<const ms_request*> rp;
+    std::vector<uint32_t> ks(reqs.size(), slot_idx);
+    for (auto& r : reqs) rp.push_back(&r);
+    uint64_t total = 0;
+    const size_t copy = fill_slot(slot, rp.data(), ks.data(), rp.size(), &total);
+    hipError_t he = hipMemcpy(slot.dev, slot.host, copy, hipMemcpyHostToDevice);
+    if (!hip_ok(he)) st = dev_err(c, he);
+    const uint32_t ppws[] = {1, 2, 4, 8, 16, 32};
+    const uint32_t unrolls[] = {1, 2};
+    const uint32_t wpcs[] = {16, 32, 64};
+    for (uint32_t u : unrolls)
+      for (uint32_t ppw : ppws)
+        for (uint32_t w : wpcs) {
+          if (st) break;
+          if (ppw < u) continue;
+          Tuning t;
+          t.ppw = ppw;
+          t.unroll = u;
+          t.waves_per_cu = w;
+          const uint32_t grid = grid_blocks_for(c, t, total);
+          const auto* hdr = reinterpret_cast<const ms::DevBatchHdr*>(slot.dev);
+          float best_ms = 1e30f;
+          for (int rep = 0; rep < 4 && !st; ++rep) {
+            he = hipEventRecord(e0, c->stream);
+            if (hip_ok(he))
+              he = ms::launch_batch(hdr, c->d_keys, t.ppw, t.unroll, grid,
+                                    (int)c->cfg.rounds, c->stream);
+            if (hip_ok(he)) he = hipEventRecord(e1, c->stream);
+            if (hip_ok(he)) he = hipEventSynchronize(e1);
+            float ms_ = 0;
+            if (hip_ok(he)) he = hipEventElapsedTime(&ms_, e0, e1);
+            if (!hip_ok(he)) {
+              st = dev_err(c, he);
+              break;
+            }
+            if (rep > 0) best_ms = std::min(best_ms, ms_);  // rep 0 warms up
+          }
+          if (!st && best_ms * 1000.0 < best.us) {
+            best = t;
+            best.us = best_ms * 1000.0;
+          }
+        }
+  }
+  if (k) (void)ms_key_destroy(c, k);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  free_slot(slot);
+  (void)hipFree(buf);
+  if (st) return st;
+  {
+    std::lock_guard<std::mutex> lk(c->tune_mu);
+    c->tuned[bucket_of(n_pages)] = best;
+  }
+  ms_tune_cache_store(c->arch.c_str(), c->cu_count, bucket_of(n_pages),
+                      best.ppw, best.unroll, best.waves_per_cu, best.us);
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    out->pages_per_wave = best.ppw;
+    out->unroll = best.unroll;
+    out->waves_per_cu = best.waves_per_cu;
+    out->us_per_launch = best.us;
+  }
+  return MS_OK;
+}
+
+ms_status ms_get_stats(ms_ctx* c, ms_stats* o) {
+  if (!c || !o) return MS_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->submitted = c->st_submitted.load();
+  o->completed = c->st_completed.load();
+  o->rejected_eagain = c->st_eagain.load();
+  o->batches = c->st_batches.load();
+  o->pages = c->st_pages.load();
+  o->prefetch_issued = c->st_pf_issued.load();
+  o->prefetch_dropped = c->st_pf_dropped.load();
+  o->cancelled = c->st_cancelled.load();
+  o->inflight_bytes = c->st_inflight_bytes.load();
+  o->max_inflight_bytes = c->st_max_inflight.load();
+  o->max_batch_requests = c->st_max_batch.load();
+  return MS_OK;
+}
+
+int ms_debug_staging_is_zero(ms_ctx* c) {
+  if (!c || !c->h_staging) return -1;
+  std::lock_guard<std::mutex> lk(c->key_mu);
+  for (uint32_t i = 0; i < MS_KEY_BYTES; ++i)
+    if (c->h_staging[i]) return 0;
+  return 1;
+}
+
+}  // extern "C"
+
+// ------------------------------------------- internal hooks for probes ---
+
+int ms_internal_device(ms_ctx* c) { return c->device; }
+int ms_internal_cu_count(ms_ctx* c) { return c->cu_count; }
+hipStream_t ms_internal_stream(ms_ctx* c, void* stream) {
+  return stream ? static_cast<hipStream_t>(stream) : c->stream;
+}
+ms_status ms_internal_check_range(ms_ctx* c, const void* p, uint64_t bytes,
+                                  uint64_t align) {
+  return check_device_range(c, p, bytes, align);
+}
+ms_status ms_internal_dev_err(ms_ctx* c, hipError_t e) { return dev_err(c, e); }

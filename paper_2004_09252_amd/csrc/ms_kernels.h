@@ -1,0 +1,78 @@
+// Internal interface between the engine (engine.cpp) and the gfx950 kernels
+// (page_cipher.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ms {
+
+constexpr uint32_t kPageBytes = 4096;
+constexpr uint32_t kWave = 64;           // CDNA wavefront width
+constexpr uint32_t kBlockThreads = 256;  // 4 waves per workgroup
+constexpr uint32_t kWavesPerBlock = kBlockThreads / kWave;
+
+enum NonceKind : uint32_t { kNonceArray = 0, kNonceLinear = 1 };
+
+// One request of a fused batch, as the batch kernel reads it from device
+// memory.  64 bytes, so a wave fetches one with scalar loads.
+struct DevReq {
+  uint64_t src;         // device address of the request's first source page
+  uint64_t dst;         // device address of its first destination page
+  uint64_t nonce;       // kNonceArray: device address of 12-byte nonces;
+                        // kNonceLinear: nonce base
+  uint64_t stride;      // kNonceLinear: nonce increment per page
+  uint64_t page_begin;  // first page of this request in the batch's
+                        // flattened page space
+  uint64_t page_end;    // one past its last page (page_begin < page_end)
+  uint32_t key_slot;    // row of the device key table
+  uint32_t kind;        // NonceKind
+  uint32_t tag;         // kNonceLinear: word 15 of the cipher state
+  uint32_t pad;
+};
+static_assert(sizeof(DevReq) == 64, "DevReq layout");
+
+// Header of a batch buffer; DevReq[n_req] follows it directly.
+struct DevBatchHdr {
+  uint64_t total_pages;  // == last request's page_end
+  uint32_t n_req;
+  uint32_t pad0;
+  uint64_t pad[6];
+};
+static_assert(sizeof(DevBatchHdr) == 64, "DevBatchHdr layout");
+
+// Arguments of one plain launch over a run of pages.
+struct PlainArgs {
+  const uint32_t* keys;  // device key table, 8 words per slot
+  const uint8_t* src;
+  uint8_t* dst;
+  const uint32_t* nonce_array;  // kNonceArray: 3 words per page
+  uint64_t nonce_base;
+  uint64_t nonce_stride;
+  uint64_t first_page;   // pages [first_page, first_page + n_pages) of the run
+  uint64_t n_pages;
+  uint32_t key_slot;
+  uint32_t nonce_tag;
+};
+
+// All launchers return the HIP status of the launch.
+hipError_t launch_plain(const PlainArgs& a, uint32_t kind, int rounds,
+                        hipStream_t stream);
+hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
+                        uint32_t pages_per_wave, uint32_t unroll,
+                        uint32_t grid_blocks, int rounds, hipStream_t stream);
+// Plain launch of the batched kernel's function pointer for graph capture.
+const void* batch_kernel_fn(uint32_t unroll, int rounds);
+
+// Calibration probes.
+hipError_t launch_copy(const void* src, void* dst, uint64_t bytes,
+                       uint32_t grid_blocks, hipStream_t stream);
+hipError_t launch_valu(uint32_t* out, uint32_t iters, uint32_t grid_blocks,
+                       hipStream_t stream);
+// Independent 32-bit VALU operations one launch of launch_valu performs.
+uint64_t valu_probe_ops(uint32_t iters, uint32_t grid_blocks);
+// Fill kernel (used instead of memset where a graph may capture it).
+hipError_t launch_fill_u32(uint32_t* dst, uint32_t value, uint64_t n_words,
+                           hipStream_t stream);
+
+}  // namespace ms

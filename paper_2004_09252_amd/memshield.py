@@ -1,0 +1,419 @@
+"""Thin ctypes binding of ``libmemshield.so`` (include/memshield.h).
+
+Every function here only marshals arguments: the cipher, the batching, the
+scheduling and the key store all run inside the native library.  The module
+fails loudly when the library has not been built; there is no fallback.
+
+Two layers:
+  * ``ms_*`` functions with the C names and C argument order (pointers are
+    Python ints, status codes are returned as ints);
+  * ``Engine`` - a small convenience wrapper that takes torch tensors for
+    device buffers and torch streams, and raises ``MemShieldError`` on a
+    non-zero status.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch  # loaded first so that the library binds to torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmemshield.so")
+
+PAGE_SIZE = 4096
+KEY_BYTES = 32
+NONCE_BYTES = 12
+
+MS_OK = 0
+MS_EINVAL = -1
+MS_ENOKEY = -2
+MS_ENOMEM = -3
+MS_EAGAIN = -4
+MS_EBUSY = -5
+MS_EDEVICE = -6
+MS_ECLOSED = -7
+MS_ETIMEDOUT = -8
+MS_ENOTSUP = -9
+MS_ECANCELED = -10
+
+MS_ENCRYPT = 0
+MS_DECRYPT = 1
+MS_NONCE_ARRAY = 0
+MS_NONCE_LINEAR = 1
+
+
+class ms_nonce(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("tag", ctypes.c_uint32),
+                ("array", ctypes.c_void_p), ("base", ctypes.c_uint64),
+                ("stride", ctypes.c_uint64)]
+
+
+class ms_request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("client", ctypes.c_uint32),
+                ("key", ctypes.c_uint64), ("src", ctypes.c_void_p),
+                ("dst", ctypes.c_void_p), ("n_pages", ctypes.c_uint64),
+                ("nonce", ms_nonce), ("priority", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class ms_config(ctypes.Structure):
+    _fields_ = [("max_keys", ctypes.c_uint32), ("rounds", ctypes.c_uint32),
+                ("queue_depth", ctypes.c_uint32),
+                ("max_batch_requests", ctypes.c_uint32),
+                ("admission_cap_bytes", ctypes.c_uint64),
+                ("inflight_batches", ctypes.c_uint32),
+                ("prefetch_depth", ctypes.c_uint32),
+                ("validate_pointers", ctypes.c_uint32),
+                ("use_graphs", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
+
+
+class ms_tuning(ctypes.Structure):
+    _fields_ = [("pages_per_wave", ctypes.c_uint32),
+                ("unroll", ctypes.c_uint32),
+                ("waves_per_cu", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32),
+                ("us_per_launch", ctypes.c_double)]
+
+
+class ms_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "submitted", "completed", "rejected_eagain", "batches", "pages",
+        "prefetch_issued", "prefetch_dropped", "cancelled", "inflight_bytes",
+        "max_inflight_bytes", "max_batch_requests")] + \
+        [("reserved", ctypes.c_uint64 * 5)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+_P = ctypes.c_void_p
+_U64 = ctypes.c_uint64
+_U32 = ctypes.c_uint32
+_I32 = ctypes.c_int32
+_SIGS = {
+    "ms_config_default": ([ctypes.POINTER(ms_config)], None),
+    "ms_status_str": ([_I32], ctypes.c_char_p),
+    "ms_init": ([ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ms_config)],
+                _I32),
+    "ms_shutdown": ([_P], _I32),
+    "ms_key_load": ([_P, ctypes.c_char_p, ctypes.POINTER(_U64)], _I32),
+    "ms_key_generate": ([_P, ctypes.POINTER(_U64)], _I32),
+    "ms_key_destroy": ([_P, _U64], _I32),
+    "ms_encrypt_pages": ([_P, _U64, _P, _P, _U64, ctypes.POINTER(ms_nonce), _P],
+                         _I32),
+    "ms_decrypt_pages": ([_P, _U64, _P, _P, _U64, ctypes.POINTER(ms_nonce), _P],
+                         _I32),
+    "ms_process_batch": ([_P, ctypes.POINTER(ms_request), ctypes.c_size_t, _P],
+                         _I32),
+    "ms_submit": ([_P, ctypes.POINTER(ms_request), ctypes.c_size_t,
+                   ctypes.POINTER(_U64)], _I32),
+    "ms_poll": ([_P, ctypes.POINTER(_U64), ctypes.c_size_t,
+                 ctypes.POINTER(_I32), _U64], _I32),
+    "ms_prefetch_hint": ([_P, ctypes.POINTER(ms_request), ctypes.c_size_t,
+                          ctypes.POINTER(_U64)], _I32),
+    "ms_cancel_client": ([_P, _U32, ctypes.POINTER(_U64)], _I32),
+    "ms_drain": ([_P, _U64], _I32),
+    "ms_autotune": ([_P, _U64, ctypes.POINTER(ms_tuning)], _I32),
+    "ms_get_tuning": ([_P, _U64, ctypes.POINTER(ms_tuning)], _I32),
+    "ms_set_tuning": ([_P, ctypes.POINTER(ms_tuning)], _I32),
+    "ms_get_stats": ([_P, ctypes.POINTER(ms_stats)], _I32),
+    "ms_debug_staging_is_zero": ([_P], ctypes.c_int),
+    "ms_probe_copy": ([_P, _P, _P, _U64, _U32, _P], _I32),
+    "ms_probe_valu": ([_P, _P, _U32, _U32, _P, ctypes.POINTER(_U64)], _I32),
+    "ms_device_cu_count": ([_P], ctypes.c_int),
+}
+
+
+def load_library(path: str | None = None):
+    """Load the native library (once).  Raises if it is not built."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise RuntimeError(
+                "libmemshield.so is not built (%s); run "
+                "`python -m paper_2004_09252_amd.build`" % p)
+        lib = ctypes.CDLL(p)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+        return lib
+
+
+def exported_symbols() -> list:
+    return list(_SIGS)
+
+
+def _L():
+    return _lib if _lib is not None else load_library()
+
+
+# ---- C-named functions (argument marshalling only) ----
+
+def ms_config_default() -> ms_config:
+    c = ms_config()
+    _L().ms_config_default(ctypes.byref(c))
+    return c
+
+
+def ms_status_str(st: int) -> str:
+    return _L().ms_status_str(st).decode()
+
+
+def ms_init(device: int = 0, config: ms_config | None = None):
+    ctx = ctypes.c_void_p()
+    st = _L().ms_init(ctypes.byref(ctx), device,
+                      ctypes.byref(config) if config is not None else None)
+    return st, ctx
+
+
+def ms_shutdown(ctx) -> int:
+    return _L().ms_shutdown(ctx)
+
+
+def ms_key_load(ctx, key: bytes):
+    h = ctypes.c_uint64()
+    st = _L().ms_key_load(ctx, bytes(key), ctypes.byref(h))
+    return st, h.value
+
+
+def ms_key_generate(ctx):
+    h = ctypes.c_uint64()
+    st = _L().ms_key_generate(ctx, ctypes.byref(h))
+    return st, h.value
+
+
+def ms_key_destroy(ctx, key: int) -> int:
+    return _L().ms_key_destroy(ctx, key)
+
+
+def ms_encrypt_pages(ctx, key, src, dst, n_pages, nonce: ms_nonce,
+                     stream=None) -> int:
+    return _L().ms_encrypt_pages(ctx, key, src, dst, n_pages,
+                                 ctypes.byref(nonce), stream)
+
+
+def ms_decrypt_pages(ctx, key, src, dst, n_pages, nonce: ms_nonce,
+                     stream=None) -> int:
+    return _L().ms_decrypt_pages(ctx, key, src, dst, n_pages,
+                                 ctypes.byref(nonce), stream)
+
+
+def _req_array(reqs):
+    if isinstance(reqs, ctypes.Array):
+        return reqs, len(reqs)
+    arr = (ms_request * len(reqs))(*reqs)
+    return arr, len(reqs)
+
+
+def ms_process_batch(ctx, reqs, stream=None) -> int:
+    arr, n = _req_array(reqs)
+    return _L().ms_process_batch(ctx, arr, n, stream)
+
+
+def ms_submit(ctx, reqs):
+    arr, n = _req_array(reqs)
+    t = (ctypes.c_uint64 * max(n, 1))()
+    st = _L().ms_submit(ctx, arr, n, t)
+    return st, list(t)[:n]
+
+
+def ms_poll(ctx, tickets, timeout_ns: int = 0):
+    n = len(tickets)
+    t = (ctypes.c_uint64 * max(n, 1))(*tickets)
+    d = (ctypes.c_int32 * max(n, 1))()
+    st = _L().ms_poll(ctx, t, n, d, timeout_ns)
+    return st, list(d)[:n]
+
+
+def ms_prefetch_hint(ctx, reqs):
+    arr, n = _req_array(reqs)
+    t = (ctypes.c_uint64 * max(n, 1))()
+    st = _L().ms_prefetch_hint(ctx, arr, n, t)
+    return st, list(t)[:n]
+
+
+def ms_cancel_client(ctx, client: int):
+    n = ctypes.c_uint64()
+    st = _L().ms_cancel_client(ctx, client, ctypes.byref(n))
+    return st, n.value
+
+
+def ms_drain(ctx, timeout_ns: int = 60 * 10**9) -> int:
+    return _L().ms_drain(ctx, timeout_ns)
+
+
+def ms_autotune(ctx, n_pages: int):
+    t = ms_tuning()
+    st = _L().ms_autotune(ctx, n_pages, ctypes.byref(t))
+    return st, t
+
+
+def ms_get_tuning(ctx, n_pages: int):
+    t = ms_tuning()
+    st = _L().ms_get_tuning(ctx, n_pages, ctypes.byref(t))
+    return st, t
+
+
+def ms_set_tuning(ctx, tuning: ms_tuning | None) -> int:
+    return _L().ms_set_tuning(ctx, ctypes.byref(tuning)
+                              if tuning is not None else None)
+
+
+def ms_get_stats(ctx):
+    s = ms_stats()
+    st = _L().ms_get_stats(ctx, ctypes.byref(s))
+    return st, s
+
+
+def ms_debug_staging_is_zero(ctx) -> int:
+    return _L().ms_debug_staging_is_zero(ctx)
+
+
+def ms_probe_copy(ctx, src, dst, nbytes, grid_blocks=0, stream=None) -> int:
+    return _L().ms_probe_copy(ctx, src, dst, nbytes, grid_blocks, stream)
+
+
+def ms_probe_valu(ctx, out, iters, grid_blocks=0, stream=None):
+    ops = ctypes.c_uint64()
+    st = _L().ms_probe_valu(ctx, out, iters, grid_blocks, stream,
+                            ctypes.byref(ops))
+    return st, ops.value
+
+
+def ms_device_cu_count(ctx) -> int:
+    return _L().ms_device_cu_count(ctx)
+
+
+# ---- convenience wrapper over torch tensors ----
+
+class MemShieldError(RuntimeError):
+    def __init__(self, st: int, what: str):
+        super().__init__("%s failed: %s (%d)" % (what, ms_status_str(st), st))
+        self.status = st
+
+
+def _check(st: int, what: str):
+    if st != MS_OK:
+        raise MemShieldError(st, what)
+
+
+def linear_nonce(base: int, stride: int, tag: int) -> ms_nonce:
+    return ms_nonce(MS_NONCE_LINEAR, tag & 0xFFFFFFFF, None,
+                    base % (1 << 64), stride % (1 << 64))
+
+
+def array_nonce(t: torch.Tensor) -> ms_nonce:
+    return ms_nonce(MS_NONCE_ARRAY, 0, t.data_ptr(), 0, 0)
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def request(key: int, src: torch.Tensor, dst: torch.Tensor, n_pages: int,
+            nonce: ms_nonce, op: int = MS_ENCRYPT, client: int = 0,
+            src_offset_pages: int = 0, dst_offset_pages: int = 0) -> ms_request:
+    return ms_request(op, client, key,
+                      src.data_ptr() + src_offset_pages * PAGE_SIZE,
+                      dst.data_ptr() + dst_offset_pages * PAGE_SIZE,
+                      n_pages, nonce, 0, 0)
+
+
+class Engine:
+    """One engine context on a GPU; buffers are torch uint8 tensors."""
+
+    def __init__(self, device: int = 0, **config):
+        cfg = ms_config_default()
+        for k, v in config.items():
+            if not hasattr(cfg, k):
+                raise TypeError("unknown config field %r" % k)
+            setattr(cfg, k, v)
+        self.device = device
+        st, self.ctx = ms_init(device, cfg)
+        _check(st, "ms_init")
+
+    def close(self):
+        if self.ctx:
+            ms_shutdown(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def key_load(self, key: bytes) -> int:
+        st, h = ms_key_load(self.ctx, key)
+        _check(st, "ms_key_load")
+        return h
+
+    def key_generate(self) -> int:
+        st, h = ms_key_generate(self.ctx)
+        _check(st, "ms_key_generate")
+        return h
+
+    def key_destroy(self, h: int):
+        _check(ms_key_destroy(self.ctx, h), "ms_key_destroy")
+
+    def _pages(self, fn, name, key, src, dst, nonce, n_pages, stream):
+        if n_pages is None:
+            n_pages = src.numel() // PAGE_SIZE
+        _check(fn(self.ctx, key, src.data_ptr(), dst.data_ptr(), n_pages,
+                  nonce, _stream_handle(stream)), name)
+
+    def encrypt_pages(self, key, src, dst, nonce, n_pages=None, stream=None):
+        self._pages(ms_encrypt_pages, "ms_encrypt_pages", key, src, dst, nonce,
+                    n_pages, stream)
+
+    def decrypt_pages(self, key, src, dst, nonce, n_pages=None, stream=None):
+        self._pages(ms_decrypt_pages, "ms_decrypt_pages", key, src, dst, nonce,
+                    n_pages, stream)
+
+    def process_batch(self, reqs, stream=None):
+        _check(ms_process_batch(self.ctx, reqs, _stream_handle(stream)),
+               "ms_process_batch")
+
+    def submit(self, reqs) -> list:
+        st, t = ms_submit(self.ctx, reqs)
+        _check(st, "ms_submit")
+        return t
+
+    def poll(self, tickets, timeout_s: float = 0.0):
+        return ms_poll(self.ctx, tickets, int(timeout_s * 1e9))
+
+    def prefetch_hint(self, reqs) -> list:
+        st, t = ms_prefetch_hint(self.ctx, reqs)
+        _check(st, "ms_prefetch_hint")
+        return t
+
+    def drain(self, timeout_s: float = 60.0):
+        _check(ms_drain(self.ctx, int(timeout_s * 1e9)), "ms_drain")
+
+    def autotune(self, n_pages: int) -> ms_tuning:
+        st, t = ms_autotune(self.ctx, n_pages)
+        _check(st, "ms_autotune")
+        return t
+
+    def stats(self) -> ms_stats:
+        st, s = ms_get_stats(self.ctx)
+        _check(st, "ms_get_stats")
+        return s
