@@ -320,7 +320,7 @@ def main():
                      "unit": "Tops/s",
                      "frac": round(achieved_ops / MI355X_INT32_VALU_OPS, 4),
                      "traffic": traffic,
-                     "kernel": "plain_pages_kernel<20, linear>",
+                     "kernel": "plain_pages_kernel<20 rounds, unroll 2, linear nonces>",
                      "avg_launch_ms": round(avg_launch_s * 1e3, 4),
                      "ops_per_launch": ops,
                      "hbm_GBps_algorithmic": round(

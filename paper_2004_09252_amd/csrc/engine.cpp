@@ -108,6 +108,8 @@ struct ms_ctx {
   hipStream_t stream = nullptr;
   int cu_count = 0;
   std::string arch;
+  uint32_t resident_plain_wpc = 0;     // resident waves/CU, plain unroll-2
+  uint32_t resident_batch_wpc[3] = {0, 0, 0};  // by unroll
 
   // ---- key store ----
   std::mutex key_mu;
@@ -248,9 +250,9 @@ uint32_t bucket_of(uint64_t n_pages) {
 
 Tuning default_tuning(uint64_t n_pages) {
   Tuning t;
-  t.unroll = 1;
-  t.ppw = n_pages >= (1u << 16) ? 8 : (n_pages >= 4096 ? 4 : 1);
-  t.waves_per_cu = 32;
+  t.unroll = 2;
+  t.ppw = n_pages >= (1u << 16) ? 8 : (n_pages >= 4096 ? 4 : 2);
+  t.waves_per_cu = 32;  // capped at the kernel's residency when launched
   return t;
 }
 
@@ -262,9 +264,22 @@ Tuning tuning_for(ms_ctx* c, uint64_t n_pages) {
   return default_tuning(n_pages);
 }
 
+// Plain launches: persistent waves, as many as fit on the chip at once, the
+// next page's loads overlapped with the current page's cipher work.
+Tuning plain_tuning(ms_ctx* c) {
+  Tuning t;
+  t.ppw = 1;
+  t.unroll = 2;
+  t.waves_per_cu = c->resident_plain_wpc ? c->resident_plain_wpc : 28;
+  return t;
+}
+
 uint32_t grid_blocks_for(ms_ctx* c, const Tuning& t, uint64_t total_pages) {
   const uint64_t items = (total_pages + t.ppw - 1) / t.ppw;
-  const uint64_t max_waves = (uint64_t)c->cu_count * t.waves_per_cu;
+  uint32_t wpc = t.waves_per_cu;
+  const uint32_t res = c->resident_batch_wpc[t.unroll == 2 ? 2 : 1];
+  if (res && wpc > res) wpc = res;  // waves beyond residency start late
+  const uint64_t max_waves = (uint64_t)c->cu_count * wpc;
   uint64_t waves = std::min<uint64_t>(std::max<uint64_t>(items, 1), max_waves);
   uint64_t blocks = (waves + ms::kWavesPerBlock - 1) / ms::kWavesPerBlock;
   return (uint32_t)std::max<uint64_t>(blocks, 1);
@@ -711,7 +726,10 @@ ms_status plain_call(ms_ctx* c, ms_key key, const void* src, void* dst,
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   const uint32_t kind =
       nonce->kind == MS_NONCE_ARRAY ? ms::kNonceArray : ms::kNonceLinear;
-  return dev_err(c, ms::launch_plain(a, kind, (int)c->cfg.rounds, s));
+  const Tuning t = plain_tuning(c);
+  return dev_err(c, ms::launch_plain(a, kind, (int)c->cfg.rounds,
+                                     (uint32_t)c->cu_count * t.waves_per_cu,
+                                     t.unroll, s));
 }
 
 ms_status install_key(ms_ctx* c, ms_key* out) {
@@ -806,6 +824,11 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
   }
   c->cu_count = prop.multiProcessorCount;
   c->arch = prop.gcnArchName;
+  c->resident_plain_wpc = ms::resident_waves_per_cu(
+      ms::plain_kernel_fn(2, (int)cfg.rounds, ms::kNonceLinear));
+  for (uint32_t u = 1; u <= 2; ++u)
+    c->resident_batch_wpc[u] =
+        ms::resident_waves_per_cu(ms::batch_kernel_fn(u, (int)cfg.rounds));
   ms_status st = MS_OK;
   const size_t key_bytes = (size_t)cfg.max_keys * MS_KEY_BYTES;
   if (!hip_ok(hipStreamCreate(&c->stream))) st = MS_EDEVICE;
@@ -1151,7 +1174,7 @@ ms_status ms_autotune(ms_ctx* c, uint64_t n_pages, ms_tuning* out) {
     if (!hip_ok(he)) st = dev_err(c, he);
     const uint32_t ppws[] = {1, 2, 4, 8, 16, 32};
     const uint32_t unrolls[] = {1, 2};
-    const uint32_t wpcs[] = {16, 32, 64};
+    const uint32_t wpcs[] = {8, 16, 24, 32};
     for (uint32_t u : unrolls)
       for (uint32_t ppw : ppws)
         for (uint32_t w : wpcs) {

@@ -56,13 +56,21 @@ struct PlainArgs {
 };
 
 // All launchers return the HIP status of the launch.
+// Plain launch: one wave per page up to `max_waves` waves, which then loop
+// over the remaining pages; `unroll` 2 overlaps a page's loads with the
+// previous page's cipher work, 1 does not.
 hipError_t launch_plain(const PlainArgs& a, uint32_t kind, int rounds,
+                        uint32_t max_waves, uint32_t unroll,
                         hipStream_t stream);
 hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
                         uint32_t pages_per_wave, uint32_t unroll,
                         uint32_t grid_blocks, int rounds, hipStream_t stream);
-// Plain launch of the batched kernel's function pointer for graph capture.
+// Kernel entry points (graph capture, occupancy queries).
 const void* batch_kernel_fn(uint32_t unroll, int rounds);
+const void* plain_kernel_fn(uint32_t unroll, int rounds, uint32_t kind);
+// Waves of `fn` (256-thread workgroups) that fit on one compute unit at once;
+// 0 if the runtime cannot say.
+uint32_t resident_waves_per_cu(const void* fn);
 
 // Calibration probes.
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes,
