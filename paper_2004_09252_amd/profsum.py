@@ -1,0 +1,140 @@
+"""Summarise rocprofv3 result databases of the page-cipher benchmark.
+
+Usage (from the repository root, on the databases a profiling run left):
+
+    python -m paper_2004_09252_amd.profsum trace  <trace.db>  <out.md>  <cmd>
+    python -m paper_2004_09252_amd.profsum traffic <fetch.db> <write.db> \
+        <out.txt> <cmd-fetch> <cmd-write>
+
+``trace`` writes the kernel-trace statistics (rocprofv3 --kernel-trace
+--stats): per kernel and grid size, the number of dispatches and their
+average, minimum and maximum duration.
+
+``traffic`` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch) into HBM bytes
+per launch of the bulk plain page kernel.  Both counters are first calibrated
+on the copy probe, which reads and writes a known 1 GiB: the factor is
+(known bytes) / (counter bytes) for each counter, and the kernel's traffic is
+its counter bytes times that factor.  The summary records the SHA-256 of the
+kernel source so that a reader (bench.py) can tell when the kernel has
+changed since the counters were taken.
+"""
+from __future__ import annotations
+
+import collections
+import hashlib
+import os
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "page_cipher.hip")
+COPY_BYTES = 1 << 30
+BULK_KERNEL = "plain_pages_kernel<20, 2, 1u>"
+COPY_KERNEL = "copy_probe_kernel"
+
+
+def _short(name: str) -> str:
+    name = name.replace("ms::(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
+    return name if len(name) <= 90 else name[:87] + "..."
+
+
+def trace(db_path: str, out_path: str, cmd: str) -> None:
+    db = sqlite3.connect(db_path)
+    groups = collections.defaultdict(list)
+    for name, gx, wx, dur in db.execute(
+            "select name, grid_x, workgroup_x, duration from kernels"):
+        groups[(name, gx // max(wx, 1))].append(dur)
+    lines = ["# rocprofv3 kernel trace: page-cipher benchmark", "",
+             "Command (from the repository root, after `cd /tmp && export "
+             "TMPDIR=/tmp`):", "", "    " + cmd, "",
+             "Durations in microseconds; `blocks` is the grid size in "
+             "256-thread workgroups.", "",
+             "| kernel | blocks | calls | avg us | min us | max us |",
+             "|---|---|---|---|---|---|"]
+    rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
+    for (name, blocks), d in rows[:25]:
+        lines.append("| %s | %d | %d | %.2f | %.2f | %.2f |" % (
+            _short(name), blocks, len(d), sum(d) / len(d) / 1e3,
+            min(d) / 1e3, max(d) / 1e3))
+    lines += ["", "rocprofv3 --stats (all dispatches of a kernel together):",
+              "", "| kernel | calls | total us | avg us | % |",
+              "|---|---|---|---|---|"]
+    for name, calls, total, avg, pct in db.execute(
+            "select name, total_calls, total_duration, average, percentage "
+            "from top_kernels limit 12"):
+        lines.append("| %s | %d | %.1f | %.2f | %.1f |" % (
+            _short(name), calls, total / 1e3, avg / 1e3, pct))
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def _counter(db_path: str, counter: str):
+    db = sqlite3.connect(db_path)
+    out = collections.defaultdict(list)
+    for name, val in db.execute(
+            "select kernel_name, value from counters_collection "
+            "where counter_name = ?", (counter,)):
+        out[name].append(val)
+    return out
+
+
+def _pick(d, needle):
+    for name, vals in d.items():
+        if needle in name:
+            return sum(vals) / len(vals), len(vals)
+    raise KeyError(needle)
+
+
+def traffic(fetch_db: str, write_db: str, out_path: str, cmd_f: str,
+            cmd_w: str) -> None:
+    f = _counter(fetch_db, "FETCH_SIZE")
+    w = _counter(write_db, "WRITE_SIZE")
+    kf, nkf = _pick(f, BULK_KERNEL)
+    cf, ncf = _pick(f, COPY_KERNEL)
+    kw, nkw = _pick(w, BULK_KERNEL)
+    cw, ncw = _pick(w, COPY_KERNEL)
+    ff = COPY_BYTES / (cf * 1024.0)
+    fw = COPY_BYTES / (cw * 1024.0)
+    fetch_b = kf * 1024.0 * ff
+    write_b = kw * 1024.0 * fw
+    algo = 2.0 * 262144 * 4096
+    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    lines = [
+        "# HBM traffic of the bulk plain page kernel (1 GiB pass, 262144 "
+        "pages), from rocprofv3 counters",
+        "# fetch command: " + cmd_f,
+        "# write command: " + cmd_w,
+        "# copy probe: reads and writes %d bytes per dispatch" % COPY_BYTES,
+        "kernel: %s" % BULK_KERNEL,
+        "fetch_size_kib_kernel: %.3f  (avg of %d dispatches)" % (kf, nkf),
+        "fetch_size_kib_copy: %.3f  (avg of %d dispatches)" % (cf, ncf),
+        "write_size_kib_kernel: %.3f  (avg of %d dispatches)" % (kw, nkw),
+        "write_size_kib_copy: %.3f  (avg of %d dispatches)" % (cw, ncw),
+        "fetch_scale: %.6f" % ff,
+        "write_scale: %.6f" % fw,
+        "fetch_bytes_per_launch: %.0f" % fetch_b,
+        "write_bytes_per_launch: %.0f" % write_b,
+        "hbm_bytes_per_launch: %.0f" % (fetch_b + write_b),
+        "algorithmic_bytes_per_launch: %.0f" % algo,
+        "traffic_over_algorithmic: %.5f" % ((fetch_b + write_b) / algo),
+        "kernel_source_sha256: %s" % digest,
+    ]
+    with open(out_path, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+
+
+def main(argv):
+    if len(argv) >= 5 and argv[1] == "trace":
+        trace(argv[2], argv[3], " ".join(argv[4:]))
+    elif len(argv) >= 7 and argv[1] == "traffic":
+        traffic(argv[2], argv[3], argv[4], argv[5], argv[6])
+    else:
+        print(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv))
