@@ -143,7 +143,8 @@ typedef struct ms_stats {
     uint64_t inflight_bytes;      /* page bytes currently admitted */
     uint64_t max_inflight_bytes;  /* high-water mark of inflight_bytes */
     uint64_t max_batch_requests;  /* largest batch formed */
-    uint64_t reserved[5];
+    uint64_t max_inflight_batches;/* most fused launches on the device at once */
+    uint64_t reserved[4];
 } ms_stats;
 
 /* Fill `cfg` with the defaults listed in ms_config. */

@@ -155,7 +155,7 @@ struct ms_ctx {
   std::atomic<uint64_t> st_submitted{0}, st_completed{0}, st_eagain{0},
       st_batches{0}, st_pages{0}, st_pf_issued{0}, st_pf_dropped{0},
       st_cancelled{0}, st_inflight_bytes{0}, st_max_inflight{0},
-      st_max_batch{0};
+      st_max_batch{0}, st_max_inflight_batches{0};
 };
 
 namespace {
@@ -546,6 +546,8 @@ bool launch_one(ms_ctx* c) {
     return true;
   }
   c->inflight.push_back(std::move(b));
+  if (c->inflight.size() > c->st_max_inflight_batches.load())
+    c->st_max_inflight_batches.store(c->inflight.size());
   return true;
 }
 
@@ -1244,6 +1246,7 @@ ms_status ms_get_stats(ms_ctx* c, ms_stats* o) {
   o->inflight_bytes = c->st_inflight_bytes.load();
   o->max_inflight_bytes = c->st_max_inflight.load();
   o->max_batch_requests = c->st_max_batch.load();
+  o->max_inflight_batches = c->st_max_inflight_batches.load();
   return MS_OK;
 }
 

@@ -82,8 +82,29 @@ class ms_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "submitted", "completed", "rejected_eagain", "batches", "pages",
         "prefetch_issued", "prefetch_dropped", "cancelled", "inflight_bytes",
-        "max_inflight_bytes", "max_batch_requests")] + \
-        [("reserved", ctypes.c_uint64 * 5)]
+        "max_inflight_bytes", "max_batch_requests", "max_inflight_batches")] + \
+        [("reserved", ctypes.c_uint64 * 4)]
+
+
+MS_SERVE_BATCHED = 0
+MS_SERVE_PLAIN = 1
+
+
+class ms_serve_trace(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("arrival_s", ctypes.c_void_p),
+                ("client", ctypes.c_void_p), ("op", ctypes.c_void_p),
+                ("n_pages", ctypes.c_void_p), ("src_page", ctypes.c_void_p),
+                ("dst_page", ctypes.c_void_p), ("va", ctypes.c_void_p),
+                ("pid", ctypes.c_void_p)]
+
+
+class ms_serve_result(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "wall_s", "data_gbps", "mean_us", "p50_us", "p90_us", "p99_us",
+        "p999_us", "max_us", "late_submit_us_max")] + \
+        [(n, ctypes.c_uint64) for n in ("completed", "eagain_retries",
+                                        "failed")] + \
+        [("reserved", ctypes.c_uint64 * 4)]
 
 
 _lib = None
@@ -124,6 +145,9 @@ _SIGS = {
     "ms_probe_copy": ([_P, _P, _P, _U64, _U32, _P], _I32),
     "ms_probe_valu": ([_P, _P, _U32, _U32, _P, ctypes.POINTER(_U64)], _I32),
     "ms_device_cu_count": ([_P], ctypes.c_int),
+    "ms_serve_run": ([_P, ctypes.POINTER(ms_serve_trace),
+                      ctypes.POINTER(_U64), _U32, _P, _U64, _P, _U64, _I32,
+                      _U32, _P, ctypes.POINTER(ms_serve_result)], _I32),
 }
 
 
@@ -290,6 +314,18 @@ def ms_probe_valu(ctx, out, iters, grid_blocks=0, stream=None):
 
 def ms_device_cu_count(ctx) -> int:
     return _L().ms_device_cu_count(ctx)
+
+
+def ms_serve_run(ctx, trace: ms_serve_trace, keys, src_pool, src_pages,
+                 dst_pool, dst_pages, mode, submit_threads, latency_out=None):
+    """latency_out: optional float64 numpy array of trace.n entries."""
+    k = (ctypes.c_uint64 * max(len(keys), 1))(*keys)
+    res = ms_serve_result()
+    lat = latency_out.ctypes.data if latency_out is not None else None
+    st = _L().ms_serve_run(ctx, ctypes.byref(trace), k, len(keys), src_pool,
+                           src_pages, dst_pool, dst_pages, mode,
+                           submit_threads, lat, ctypes.byref(res))
+    return st, res
 
 
 # ---- convenience wrapper over torch tensors ----

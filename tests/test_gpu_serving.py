@@ -1,0 +1,289 @@
+"""GPU tests of the serving path: continuous batching through ms_submit /
+ms_poll, admission by device memory, back-pressure, cancellation, prefetch
+hints, and the native load generator.  Every output checked here is compared
+with the CPU oracle on that request alone (tolerance 0: the cipher is integer
+arithmetic)."""
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_09252_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+HOST_THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _note(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ms():
+    from paper_2004_09252_amd import memshield
+    return memshield
+
+
+def _oracle_req(key, va, pid, data):
+    n = data.size // 4096
+    return oracle.cipher_pages(key, oracle.nonces_linear(n, va, 4096, pid),
+                               data.reshape(n, 4096),
+                               threads=HOST_THREADS).reshape(-1)
+
+
+class _Reqs:
+    """n requests from several clients over one device input pool, each with
+    its own slot in each of two output buffers."""
+
+    def __init__(self, ms, eng, seed, n, max_pages=256, n_clients=8):
+        import torch
+        rng = np.random.default_rng(seed)
+        self.kbytes = [rng.bytes(32) for _ in range(n_clients)]
+        self.keys = [eng.key_load(k) for k in self.kbytes]
+        self.pages = workloads.log_uniform_pages(rng, max_pages, size=n)
+        self.client = rng.integers(0, n_clients, size=n)
+        self.va = workloads.VA_BASE + 4096 * rng.integers(0, 1 << 20, size=n)
+        self.pid = 1000 + self.client
+        self.off = np.concatenate([[0], np.cumsum(self.pages)[:-1]])
+        total = int(self.pages.sum())
+        self.host = workloads.random_pages(rng, total).reshape(-1)
+        self.src = torch.from_numpy(self.host).to("cuda")
+        self.dst_a = torch.zeros_like(self.src)
+        self.dst_b = torch.zeros_like(self.src)
+        self.ms = ms
+
+    def req(self, i, dst):
+        ms = self.ms
+        return ms.request(self.keys[self.client[i]], self.src, dst,
+                          int(self.pages[i]),
+                          ms.linear_nonce(int(self.va[i]), 4096,
+                                          int(self.pid[i])),
+                          op=int(i % 2), client=int(self.client[i]),
+                          src_offset_pages=int(self.off[i]),
+                          dst_offset_pages=int(self.off[i]))
+
+    def expect(self, i):
+        s = int(self.off[i]) * 4096
+        e = s + int(self.pages[i]) * 4096
+        return _oracle_req(self.kbytes[self.client[i]], int(self.va[i]),
+                           int(self.pid[i]), self.host[s:e])
+
+    def slice(self, t, i):
+        s = int(self.off[i]) * 4096
+        return t[s:s + int(self.pages[i]) * 4096].cpu().numpy()
+
+
+def test_alone_equals_mix_equals_oracle(ms):
+    """Each request's result is the same submitted alone (one at a time,
+    waiting for each) and in the mix (all submitted concurrently from 8
+    threads, batched by the scheduler)."""
+    _note("alone vs mix, 96 requests")
+    eng = ms.Engine(0)
+    try:
+        r = _Reqs(ms, eng, seed=41, n=96)
+        for i in range(96):
+            t = eng.submit([r.req(i, r.dst_a)])
+            st, done = eng.poll(t, timeout_s=30)
+            assert st == 0 and done == [1]
+        before = eng.stats()
+        tickets = [None] * 96
+
+        def submitter(k):
+            for i in range(k, 96, 8):
+                tickets[i] = eng.submit([r.req(i, r.dst_b)])[0]
+
+        th = [threading.Thread(target=submitter, args=(k,)) for k in range(8)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        st, done = eng.poll(tickets, timeout_s=60)
+        assert st == 0 and all(d == 1 for d in done)
+        after = eng.stats()
+        # the mix was served by fewer fused launches than requests
+        assert after.batches - before.batches < 96
+        assert after.max_batch_requests > 1
+        for i in range(96):
+            a = r.slice(r.dst_a, i)
+            b = r.slice(r.dst_b, i)
+            assert np.array_equal(a, b), "request %d alone != mix" % i
+            assert np.array_equal(a, r.expect(i)), "request %d != oracle" % i
+    finally:
+        eng.close()
+
+
+def test_batches_overlap_on_device(ms):
+    """A request that arrives while another batch runs is launched as its own
+    batch on another stream before the first finishes."""
+    _note("overlap")
+    eng = ms.Engine(0)
+    try:
+        r = _Reqs(ms, eng, seed=42, n=2, max_pages=2)
+        import torch
+        big_pages = 65536
+        big = torch.zeros(big_pages * 4096, dtype=torch.uint8, device="cuda")
+        # a narrow grid for the big request leaves room on the chip
+        assert ms.ms_set_tuning(eng.ctx, ms.ms_tuning(64, 1, 2, 0, 0.0)) == 0
+        k = r.keys[0]
+        tb = eng.submit([ms.request(k, big, big, big_pages,
+                                    ms.linear_nonce(0, 1, 0))])
+        t0 = time.time()
+        while eng.stats().batches < 1 and time.time() - t0 < 10:
+            pass
+        ts = eng.submit([r.req(0, r.dst_a)])
+        st, d_small = eng.poll(ts, timeout_s=30)
+        assert st == 0 and d_small == [1]
+        st2, d_big = eng.poll(tb, timeout_s=0)
+        stats = eng.stats()
+        st, _ = eng.poll(tb, timeout_s=30)
+        assert st == 0
+        assert stats.max_inflight_batches >= 2
+        # the small request finished while the big one was still running
+        assert d_big == [0], "big request finished first: no overlap shown"
+        assert np.array_equal(r.slice(r.dst_a, 0), r.expect(0))
+    finally:
+        ms.ms_set_tuning(eng.ctx, None)
+        eng.close()
+
+
+def test_admission_cap_bounds_inflight_bytes(ms):
+    _note("admission cap")
+    cap = 64 * 4096
+    eng = ms.Engine(0, admission_cap_bytes=cap)
+    try:
+        r = _Reqs(ms, eng, seed=43, n=60, max_pages=32)
+        tickets = eng.submit([r.req(i, r.dst_a) for i in range(60)])
+        st, done = eng.poll(tickets, timeout_s=60)
+        assert st == 0 and all(d == 1 for d in done)
+        s = eng.stats()
+        assert 0 < s.max_inflight_bytes <= cap
+        for i in (0, 17, 59):
+            assert np.array_equal(r.slice(r.dst_a, i), r.expect(i))
+        # a single request larger than the cap can never be admitted
+        import torch
+        big = torch.zeros(65 * 4096, dtype=torch.uint8, device="cuda")
+        bad = ms.request(r.keys[0], big, big, 65, ms.linear_nonce(0, 1, 0))
+        st, _ = ms.ms_submit(eng.ctx, [bad])
+        assert st == ms.MS_EINVAL
+    finally:
+        eng.close()
+
+
+def test_queue_full_is_eagain_and_all_or_nothing(ms):
+    _note("eagain")
+    eng = ms.Engine(0, queue_depth=4)
+    try:
+        r = _Reqs(ms, eng, seed=44, n=5, max_pages=4)
+        st, _ = ms.ms_submit(eng.ctx, [r.req(i, r.dst_a) for i in range(5)])
+        assert st == ms.MS_EAGAIN
+        assert eng.stats().submitted == 0
+        t = eng.submit([r.req(i, r.dst_a) for i in range(4)])
+        st, done = eng.poll(t, timeout_s=30)
+        assert st == 0 and done == [1] * 4
+    finally:
+        eng.close()
+
+
+def test_cancel_client_keeps_others_exact(ms):
+    """Cancelling a client drops its queued requests (their tickets read
+    MS_ECANCELED); every other client's results stay bit-exact."""
+    _note("cancel client")
+    eng = ms.Engine(0, admission_cap_bytes=16 * 4096)
+    try:
+        r = _Reqs(ms, eng, seed=45, n=120, max_pages=16, n_clients=3)
+        tickets = eng.submit([r.req(i, r.dst_a) for i in range(120)])
+        st, n_cancel = ms.ms_cancel_client(eng.ctx, 1)
+        assert st == 0
+        st, done = eng.poll(tickets, timeout_s=60)
+        assert st == 0
+        cancelled = 0
+        for i in range(120):
+            if r.client[i] == 1:
+                assert done[i] in (1, ms.MS_ECANCELED)
+                cancelled += done[i] == ms.MS_ECANCELED
+            else:
+                assert done[i] == 1
+                assert np.array_equal(r.slice(r.dst_a, i), r.expect(i))
+        assert cancelled == n_cancel and cancelled > 0
+    finally:
+        eng.close()
+
+
+def test_key_destroy_while_queued_is_ebusy(ms):
+    _note("destroy busy")
+    eng = ms.Engine(0, admission_cap_bytes=4 * 4096)
+    try:
+        r = _Reqs(ms, eng, seed=46, n=400, max_pages=4, n_clients=1)
+        tickets = eng.submit([r.req(i, r.dst_a) for i in range(400)])
+        # 400 requests admitted one or two at a time are still queued
+        assert ms.ms_key_destroy(eng.ctx, r.keys[0]) == ms.MS_EBUSY
+        st, done = eng.poll(tickets, timeout_s=60)
+        assert st == 0 and all(d == 1 for d in done)
+        eng.drain()
+        assert ms.ms_key_destroy(eng.ctx, r.keys[0]) == ms.MS_OK
+    finally:
+        eng.close()
+
+
+def test_prefetch_hints_run_or_drop(ms):
+    _note("prefetch hints")
+    eng = ms.Engine(0, prefetch_depth=4)
+    try:
+        r = _Reqs(ms, eng, seed=47, n=8, max_pages=8)
+        dropped = eng.prefetch_hint([r.req(i, r.dst_a) for i in range(5)])
+        assert dropped == [0] * 5         # more than the queue holds
+        st, d = eng.poll(dropped)
+        assert d == [ms.MS_ECANCELED] * 5
+        t = eng.prefetch_hint([r.req(i, r.dst_b) for i in range(4)])
+        st, d = eng.poll(t, timeout_s=30)
+        assert st == 0
+        for i in range(4):
+            if d[i] == 1:
+                assert np.array_equal(r.slice(r.dst_b, i), r.expect(i))
+            else:
+                assert d[i] == ms.MS_ECANCELED
+        s = eng.stats()
+        assert s.prefetch_dropped >= 5
+    finally:
+        eng.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_loadgen_poisson_sample_exact(ms, mode):
+    """Poisson arrivals (20k req/s, 0.5 s) through the native load
+    generator; every 25th request's output is checked against the oracle."""
+    _note("loadgen mode=%d" % mode)
+    import torch
+    from paper_2004_09252_amd import serving
+    pool_pages = 16384
+    w = workloads.serving(seed=4, rate_hz=20000, duration_s=0.5,
+                          pool_pages=pool_pages)
+    eng = ms.Engine(0)
+    try:
+        keys = [eng.key_load(k) for k in w.keys]
+        src = torch.empty(pool_pages * 4096, dtype=torch.uint8, device="cuda")
+        serving.fill_pool(src, seed=4)
+        lay = serving.layout(w, ring_pages=8192, sample_every=25)
+        dst = torch.zeros(lay.dst_pages * 4096, dtype=torch.uint8,
+                          device="cuda")
+        res, lat = serving.run(eng, lay, keys, src, dst, mode)
+        assert res.completed == lay.trace.n and res.failed == 0
+        assert res.p50_us > 0 and res.p99_us >= res.p50_us
+        assert np.all(lat > 0)
+        a = lay.arrays
+        for i, inp, out in serving.sampled_outputs(lay, src, dst):
+            c = int(a["client"][i])
+            want = _oracle_req(w.keys[c], int(a["va"][i]), int(a["pid"][i]),
+                               inp)
+            assert np.array_equal(out, want), "request %d" % i
+        if mode == 0:
+            s = eng.stats()
+            assert s.batches <= s.submitted
+    finally:
+        eng.close()
