@@ -15,9 +15,10 @@ the achieved rate is the algorithmic operation count of one launch divided
 by the launch's average duration, timed with HIP events on the stream the
 kernels run on.  ``cpu_baseline`` times the CPU oracle on the host cores.
 
-``--batched`` adds the fused batched workload (512 requests from 32 clients,
-one launch) against 512 plain launches; ``--serving`` adds a short
-continuous-batching run with p50/p99 latency.  Only one GPU is used.
+``batched`` adds the fused batched workload (512 requests from 32 clients,
+one launch) against 512 plain launches; ``serving`` adds the Poisson serving
+workload (continuous batching vs a plain launch per request, p50/p99) and a
+rate sweep for the equal-p99 comparison.  Only one GPU is used.
 """
 from __future__ import annotations
 
@@ -261,6 +262,92 @@ def calibrate(ms, torch):
             "note": "best of 5; copy counts read + write bytes"}
 
 
+def run_serving(args, ms, torch):
+    """Poisson arrivals (20k req/s, 10 s, 1..256 pages log-uniform, 64 clients,
+    admission cap 8 GiB) through continuous batching and through one plain
+    launch per request; then a short rate sweep to compare GB/s at equal p99.
+    Inputs are slices of a seeded 8 GiB device pool; every 100th request
+    writes to its own slot and is checked against the oracle."""
+    import numpy as np
+    import oracle
+    from paper_2004_09252_amd import serving, workloads
+    pool_pages = args.serving_pool_pages
+    w = workloads.serving(seed=4, rate_hz=20000.0,
+                          duration_s=args.serving_duration,
+                          pool_pages=pool_pages)
+    eng = ms.Engine(0)
+    keys = [eng.key_load(k) for k in w.keys]
+    src = torch.empty(pool_pages * 4096, dtype=torch.uint8, device="cuda")
+    serving.fill_pool(src, seed=4)
+    ring = min(pool_pages, 2097152)
+    lay = serving.layout(w, ring_pages=ring, sample_every=100)
+    dst = torch.zeros(lay.dst_pages * 4096, dtype=torch.uint8, device="cuda")
+    out = {"workload": "Poisson %.0f req/s for %.1f s, %d requests, 1..256 "
+                       "pages log-uniform, 64 clients, 8 GiB admission cap, "
+                       "%d-page input pool" % (20000, args.serving_duration,
+                                               lay.trace.n, pool_pages)}
+    checked = 0
+    for name, mode in (("served_batched", ms.MS_SERVE_BATCHED),
+                       ("plain_per_request", ms.MS_SERVE_PLAIN)):
+        log("serving %s" % name)
+        dst.zero_()
+        before = eng.stats()
+        res, lat = serving.run(eng, lay, keys, src, dst, mode)
+        r = serving.summarize(res)
+        after = eng.stats()
+        if mode == ms.MS_SERVE_BATCHED:
+            nb = after.batches - before.batches
+            r["batches"] = int(nb)
+            r["requests_per_batch"] = round(res.completed / max(nb, 1), 2)
+            r["max_inflight_batches"] = int(after.max_inflight_batches)
+        a = lay.arrays
+        for i, inp, o in serving.sampled_outputs(lay, src, dst):
+            c = int(a["client"][i])
+            n = inp.size // 4096
+            want = oracle.cipher_pages(
+                w.keys[c], oracle.nonces_linear(n, int(a["va"][i]), 4096,
+                                                int(a["pid"][i])),
+                inp.reshape(n, 4096), threads=16).reshape(-1)
+            if not np.array_equal(o, want):
+                raise RuntimeError("serving output %d differs" % i)
+            checked += 1
+        r["sample_checked_vs_oracle"] = int(len(lay.sample))
+        out[name] = r
+    # rate sweep: equal-p99 comparison
+    sweep = []
+    for rate in args.sweep_rates:
+        ws = workloads.serving(seed=40 + int(rate // 1000), rate_hz=rate,
+                               duration_s=args.sweep_duration,
+                               pool_pages=pool_pages)
+        ls = serving.layout(ws, ring_pages=ring, sample_every=0)
+        ks = keys   # same 64 client keys
+        row = {"rate_req_s": rate, "requests": int(ls.trace.n)}
+        for name, mode in (("served", ms.MS_SERVE_BATCHED),
+                           ("plain", ms.MS_SERVE_PLAIN)):
+            log("sweep %s %d req/s" % (name, rate))
+            res, _ = serving.run(eng, ls, ks, src, dst, mode)
+            row[name + "_GBps"] = round(res.data_gbps, 2)
+            row[name + "_p50_us"] = round(res.p50_us, 1)
+            row[name + "_p99_us"] = round(res.p99_us, 1)
+        sweep.append(row)
+    out["rate_sweep"] = sweep
+    slo = max(out["served_batched"]["p99_us"],
+              out["plain_per_request"]["p99_us"])
+    best = {}
+    for m in ("served", "plain"):
+        ok = [r[m + "_GBps"] for r in sweep if r[m + "_p99_us"] <= slo]
+        best[m] = max(ok) if ok else None
+    out["equal_p99"] = {"p99_bound_us": round(slo, 1),
+                        "served_GBps": best["served"],
+                        "plain_GBps": best["plain"]}
+    for k in keys:
+        eng.key_destroy(k)
+    eng.close()
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,7 +357,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-pages", type=int, default=262144)
     ap.add_argument("--cpu-reps", type=int, default=1)
-    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-duration", type=float, default=10.0)
+    ap.add_argument("--serving-pool-pages", type=int, default=2097152)
+    ap.add_argument("--sweep-rates", type=float, nargs="*",
+                    default=[20000, 50000, 100000, 200000, 400000])
+    ap.add_argument("--sweep-duration", type=float, default=1.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the page cipher needs no "
@@ -332,9 +425,11 @@ def main():
     }
     log("calibration probes")
     line["calibration"] = calibrate(ms, torch)
-    if args.batched:
+    if not args.no_batched:
         log("batched workload")
         line["batched"] = run_batched(args, ms, torch)
+    if not args.no_serving:
+        line["serving"] = run_serving(args, ms, torch)
     if not args.no_cpu_baseline:
         sp = min(args.cpu_sample_pages, n)
         log("cpu baseline on %d pages" % sp)

@@ -1,0 +1,509 @@
+// Page-access predictor kernels for gfx950 (include/memshield_mlp.h).
+//
+// Matrix products use the bf16 matrix-core instruction
+// v_mfma_f32_16x16x16bf16_1k: a wave multiplies a 16x16 bf16 tile of A by a
+// 16x16 bf16 tile of B into a 16x16 float32 accumulator.  Operand layout for
+// lane l of the wave: A row (l % 16), K elements 4*(l/16)..+3; B column
+// (l % 16), K elements 4*(l/16)..+3; accumulator column (l % 16), rows
+// 4*(l/16)..+3.  A workgroup of four waves computes a 64x64 output tile,
+// each wave a 32x32 quarter (2x2 MFMA tiles), staging 64x32 / 32x64 bf16
+// tiles of A and B through LDS per K step of 32.  Transposed operands are
+// handled in the LDS staging, so one kernel serves the forward products and
+// both gradient products.  The epilogue adds a bias, applies ReLU or a ReLU
+// mask taken from a stored activation, and writes float32 and/or bf16.
+//
+// Everything else (embedding gather and its deterministic scatter-add,
+// softmax cross-entropy, bias gradients, Adam, top-k) is elementwise or a
+// small reduction on the vector ALUs.  Reductions run in a fixed order, so
+// results are bit-reproducible run to run.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "memshield_mlp.h"
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 64;
+constexpr int kTileK = 32;
+
+__device__ __forceinline__ float bf2f(uint16_t h) {
+  return __uint_as_float((uint32_t)h << 16);
+}
+
+// float32 -> bfloat16, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+struct GemmArgs {
+  const uint16_t* A;  // logical M x K: A[m*lda+k], or A[k*lda+m] if transA
+  const uint16_t* B;  // logical K x N: B[k*ldb+n], or B[n*ldb+k] if transB
+  const uint16_t* bias;  // N entries or null
+  const uint16_t* mask;  // M x N (ld ldm) or null: out *= (mask > 0)
+  float* outF;           // M x N float32 (ld ldo) or null
+  uint16_t* outH;        // M x N bf16 (ld ldh) or null
+  int M, N, K;
+  int lda, ldb, ldm, ldo, ldh;
+  int transA, transB, relu;
+};
+
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
+  __shared__ uint16_t As[kTile][kTileK + 8];
+  __shared__ uint16_t Bs[kTileK][kTile + 8];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < g.K; k0 += kTileK) {
+#pragma unroll
+    for (int t = 0; t < (kTile * kTileK) / 256; ++t) {
+      const int idx = tid + 256 * t;
+      int m, k;
+      if (g.transA) { m = idx % kTile; k = idx / kTile; }
+      else { m = idx / kTileK; k = idx % kTileK; }
+      const int gm = m0 + m, gk = k0 + k;
+      uint16_t v = 0;
+      if (gm < g.M && gk < g.K)
+        v = g.transA ? g.A[(size_t)gk * g.lda + gm] : g.A[(size_t)gm * g.lda + gk];
+      As[m][k] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < (kTile * kTileK) / 256; ++t) {
+      const int idx = tid + 256 * t;
+      int k, n;
+      if (g.transB) { n = idx / kTileK; k = idx % kTileK; }
+      else { k = idx / kTile; n = idx % kTile; }
+      const int gn = n0 + n, gk = k0 + k;
+      uint16_t v = 0;
+      if (gn < g.N && gk < g.K)
+        v = g.transB ? g.B[(size_t)gn * g.ldb + gk] : g.B[(size_t)gk * g.ldb + gn];
+      Bs[k][n] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kTileK; kk += 16) {
+      const int kb = kk + 4 * (lane >> 4);
+      v4s a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = wm * 32 + i * 16 + (lane & 15);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[i][t] = (short)As[r][kb + t];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int c = wn * 32 + j * 16 + (lane & 15);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) b[j][t] = (short)Bs[kb + t][c];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+              a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (row >= g.M || col >= g.N) continue;
+        float v = acc[i][j][r];
+        if (g.bias) v += bf2f(g.bias[col]);
+        if (g.relu) v = v > 0.f ? v : 0.f;
+        if (g.mask && !(bf2f(g.mask[(size_t)row * g.ldm + col]) > 0.f)) v = 0.f;
+        if (g.outF) g.outF[(size_t)row * g.ldo + col] = v;
+        if (g.outH) g.outH[(size_t)row * g.ldh + col] = f2bf(v);
+      }
+}
+
+// x[b][s*D + d] = E[ids[b][s]][d]; ids outside [0, V) are clamped.
+__global__ void embed_gather_kernel(const uint16_t* __restrict__ E,
+                                    const int32_t* __restrict__ ids, int B,
+                                    int C, int D, int V,
+                                    uint16_t* __restrict__ x) {
+  const int64_t n = (int64_t)B * C * D;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t bs = i / D;
+    const int d = (int)(i % D);
+    int id = ids[bs];
+    id = id < 0 ? 0 : (id >= V ? V - 1 : id);
+    x[i] = E[(int64_t)id * D + d];
+  }
+}
+
+// dE[v][d] = sum over (b, s) with ids[b][s] == v of dx[b][s*D + d], summed in
+// (b, s) order: one workgroup per vocabulary row, deterministic.
+__global__ void embed_scatter_kernel(const float* __restrict__ dx,
+                                     const int32_t* __restrict__ ids, int B,
+                                     int C, int D, int V,
+                                     float* __restrict__ dE) {
+  const int v = blockIdx.x;
+  for (int d = threadIdx.x; d < D; d += blockDim.x) {
+    float acc = 0.f;
+    for (int bs = 0; bs < B * C; ++bs) {
+      int id = ids[bs];
+      id = id < 0 ? 0 : (id >= V ? V - 1 : id);
+      if (id == v) acc += dx[(int64_t)bs * D + d];
+    }
+    dE[(int64_t)v * D + d] = acc;
+  }
+}
+
+// One workgroup per row: loss_row[b] and dlogits = (softmax - onehot) / B.
+__global__ __launch_bounds__(256) void softmax_ce_kernel(
+    const float* __restrict__ logits, const int32_t* __restrict__ targets,
+    int B, int V, float* __restrict__ row_loss, float* __restrict__ dlF,
+    uint16_t* __restrict__ dlH) {
+  __shared__ float red[256];
+  const int b = blockIdx.x;
+  const float* row = logits + (int64_t)b * V;
+  float mx = -INFINITY;
+  for (int i = threadIdx.x; i < V; i += 256) mx = fmaxf(mx, row[i]);
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  mx = red[0];
+  __syncthreads();
+  float sum = 0.f;
+  for (int i = threadIdx.x; i < V; i += 256) sum += expf(row[i] - mx);
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  sum = red[0];
+  int t = targets[b];
+  t = t < 0 ? 0 : (t >= V ? V - 1 : t);
+  const float inv_b = 1.f / (float)B;
+  for (int i = threadIdx.x; i < V; i += 256) {
+    float p = expf(row[i] - mx) / sum;
+    if (i == t) p -= 1.f;
+    p *= inv_b;
+    dlF[(int64_t)b * V + i] = p;
+    dlH[(int64_t)b * V + i] = f2bf(p);
+  }
+  if (threadIdx.x == 0) row_loss[b] = logf(sum) + mx - row[t];
+}
+
+// loss = mean of row_loss (one workgroup, fixed order).
+__global__ void mean_kernel(const float* __restrict__ v, int n,
+                            float* __restrict__ out) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < n; i += 256) s += v[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0] / (float)n;
+}
+
+// out[n] = sum over m of in[m][n] (float32), rows summed in order.
+__global__ void colsum_kernel(const float* __restrict__ in, int M, int N,
+                              int ld, float* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int m = 0; m < M; ++m) s += in[(int64_t)m * ld + n];
+  out[n] = s;
+}
+
+__global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m,
+                            float* __restrict__ v, const float* __restrict__ g,
+                            uint16_t* __restrict__ wh, uint64_t n, float lr,
+                            float b1, float b2, float eps, float c1,
+                            float c2) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi * c1;
+    const float vh = vi * c2;
+    const float wi = w[i] - lr * mh / (sqrtf(vh) + eps);
+    w[i] = wi;
+    wh[i] = f2bf(wi);
+  }
+}
+
+__global__ void to_bf16_kernel(const float* __restrict__ s,
+                               uint16_t* __restrict__ d, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    d[i] = f2bf(s[i]);
+}
+
+// One wave per row: k rounds of (lane-local best, wave reduction); the
+// order is (value descending, id ascending); NaN counts as -inf.
+__global__ __launch_bounds__(64) void topk_kernel(
+    const float* __restrict__ logits, int V, int k, int exclude,
+    int32_t* __restrict__ out) {
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const float* row = logits + (int64_t)b * V;
+  int chosen[16];
+  for (int r = 0; r < k; ++r) {
+    float bv = -INFINITY;
+    int bi = 0x7fffffff;
+    for (int i = lane; i < V; i += 64) {
+      if (i == exclude) continue;
+      bool used = false;
+      for (int q = 0; q < r; ++q) used |= chosen[q] == i;
+      if (used) continue;
+      float x = row[i];
+      if (x != x) x = -INFINITY;
+      if (x > bv || (x == bv && i < bi)) { bv = x; bi = i; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const float ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    chosen[r] = bi;
+    if (lane == 0) out[(int64_t)b * k + r] = bi;
+  }
+}
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+bool shape_ok(const ms_mlp_shape* s) {
+  if (!s) return false;
+  const int64_t cd = (int64_t)s->context * s->embed;
+  return s->vocab >= 64 && s->vocab % 64 == 0 && s->context >= 1 &&
+         s->embed >= 1 && cd % 32 == 0 && s->hidden >= 32 &&
+         s->hidden % 32 == 0 && cd <= (1 << 16) && s->hidden <= (1 << 14) &&
+         s->vocab <= (1 << 16);
+}
+
+struct Ws {
+  uint16_t *x, *h1, *h2, *dlH, *dz2H, *dz1H;
+  float *logits, *dlF, *dz2F, *dz1F, *dxF, *row_loss;
+  uint64_t bytes;
+};
+
+Ws carve(const ms_mlp_shape* s, int64_t Bm, uint8_t* base) {
+  const int64_t CD = (int64_t)s->context * s->embed, H = s->hidden,
+                V = s->vocab;
+  Ws w;
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    uint8_t* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  w.x = (uint16_t*)take(Bm * CD * 2);
+  w.h1 = (uint16_t*)take(Bm * H * 2);
+  w.h2 = (uint16_t*)take(Bm * H * 2);
+  w.dlH = (uint16_t*)take(Bm * V * 2);
+  w.dz2H = (uint16_t*)take(Bm * H * 2);
+  w.dz1H = (uint16_t*)take(Bm * H * 2);
+  w.logits = (float*)take(Bm * V * 4);
+  w.dlF = (float*)take(Bm * V * 4);
+  w.dz2F = (float*)take(Bm * H * 4);
+  w.dz1F = (float*)take(Bm * H * 4);
+  w.dxF = (float*)take(Bm * CD * 4);
+  w.row_loss = (float*)take(Bm * 4);
+  w.bytes = off;
+  return w;
+}
+
+hipError_t gemm(const GemmArgs& g, hipStream_t s) {
+  dim3 grid((g.N + kTile - 1) / kTile, (g.M + kTile - 1) / kTile);
+  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+GemmArgs gemm_args(const uint16_t* A, int lda, int transA, const uint16_t* B,
+                   int ldb, int transB, int M, int N, int K) {
+  GemmArgs g;
+  memset(&g, 0, sizeof(g));
+  g.A = A; g.lda = lda; g.transA = transA;
+  g.B = B; g.ldb = ldb; g.transB = transB;
+  g.M = M; g.N = N; g.K = K;
+  return g;
+}
+
+int grid_for(uint64_t n) {
+  uint64_t b = (n + 255) / 256;
+  return (int)(b > 4096 ? 4096 : (b ? b : 1));
+}
+
+// Forward into the workspace; logits to `logits`.
+hipError_t forward_impl(const ms_mlp_shape* s, const uint16_t* P,
+                        const uint64_t off[7], const int32_t* ids, int B,
+                        float* logits, const Ws& w, hipStream_t st) {
+  const int CD = s->context * s->embed, H = s->hidden, V = s->vocab;
+  const int64_t n = (int64_t)B * CD;
+  hipLaunchKernelGGL(embed_gather_kernel, dim3(grid_for(n)), dim3(256), 0, st,
+                     P + off[0], ids, B, s->context, s->embed, V, w.x);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  GemmArgs g = gemm_args(w.x, CD, 0, P + off[1], H, 0, B, H, CD);
+  g.bias = P + off[2]; g.relu = 1; g.outH = w.h1; g.ldh = H;
+  if ((e = gemm(g, st)) != hipSuccess) return e;
+  g = gemm_args(w.h1, H, 0, P + off[3], H, 0, B, H, H);
+  g.bias = P + off[4]; g.relu = 1; g.outH = w.h2; g.ldh = H;
+  if ((e = gemm(g, st)) != hipSuccess) return e;
+  g = gemm_args(w.h2, H, 0, P + off[5], V, 0, B, V, H);
+  g.bias = P + off[6]; g.outF = logits; g.ldo = V;
+  return gemm(g, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t ms_mlp_offsets(const ms_mlp_shape* s, uint64_t off[7]) {
+  if (!shape_ok(s) || !off) return 0;
+  const uint64_t CD = (uint64_t)s->context * s->embed, H = s->hidden,
+                 V = s->vocab, D = s->embed;
+  const uint64_t sizes[7] = {V * D, CD * H, H, H * H, H, H * V, V};
+  uint64_t o = 0;
+  for (int i = 0; i < 7; ++i) {
+    off[i] = o;
+    o += sizes[i];
+  }
+  return o;
+}
+
+uint64_t ms_mlp_workspace_bytes(const ms_mlp_shape* s, int32_t max_batch) {
+  if (!shape_ok(s) || max_batch < 1 || max_batch > (1 << 20)) return 0;
+  return carve(s, max_batch, nullptr).bytes;
+}
+
+ms_status ms_mlp_forward(const ms_mlp_shape* s, const uint16_t* params,
+                         const int32_t* ids, int32_t batch, float* logits,
+                         void* workspace, uint64_t ws_bytes, void* stream) {
+  uint64_t off[7];
+  if (!ms_mlp_offsets(s, off) || !params || !ids || !logits || !workspace ||
+      batch < 1)
+    return MS_EINVAL;
+  const Ws w = carve(s, batch, static_cast<uint8_t*>(workspace));
+  if (w.bytes > ws_bytes) return MS_EINVAL;
+  hipError_t e = forward_impl(s, params, off, ids, batch, logits, w,
+                              static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? MS_OK : MS_EDEVICE;
+}
+
+ms_status ms_mlp_backward(const ms_mlp_shape* s, const uint16_t* P,
+                          const int32_t* ids, const int32_t* targets,
+                          int32_t B, float* G, float* loss, void* workspace,
+                          uint64_t ws_bytes, void* stream) {
+  uint64_t off[7];
+  if (!ms_mlp_offsets(s, off) || !P || !ids || !targets || !G || !loss ||
+      !workspace || B < 1)
+    return MS_EINVAL;
+  const Ws w = carve(s, B, static_cast<uint8_t*>(workspace));
+  if (w.bytes > ws_bytes) return MS_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int CD = s->context * s->embed, H = s->hidden, V = s->vocab;
+  hipError_t e = forward_impl(s, P, off, ids, B, w.logits, w, st);
+  if (e != hipSuccess) return MS_EDEVICE;
+  hipLaunchKernelGGL(softmax_ce_kernel, dim3(B), dim3(256), 0, st, w.logits,
+                     targets, B, V, w.row_loss, w.dlF, w.dlH);
+  hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, st, w.row_loss, B,
+                     loss);
+  // output layer: dW3 = h2^T dl, db3 = colsum(dl), dz2 = (dl W3^T) * (h2>0)
+  GemmArgs g = gemm_args(w.h2, H, 1, w.dlH, V, 0, H, V, B);
+  g.outF = G + off[5]; g.ldo = V;
+  if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
+  hipLaunchKernelGGL(colsum_kernel, dim3((V + 255) / 256), dim3(256), 0, st,
+                     w.dlF, B, V, V, G + off[6]);
+  g = gemm_args(w.dlH, V, 0, P + off[5], V, 1, B, H, V);
+  g.mask = w.h2; g.ldm = H; g.outF = w.dz2F; g.ldo = H; g.outH = w.dz2H;
+  g.ldh = H;
+  if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
+  // layer 2: dW2 = h1^T dz2, db2 = colsum(dz2), dz1 = (dz2 W2^T) * (h1>0)
+  g = gemm_args(w.h1, H, 1, w.dz2H, H, 0, H, H, B);
+  g.outF = G + off[3]; g.ldo = H;
+  if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
+  hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256), dim3(256), 0, st,
+                     w.dz2F, B, H, H, G + off[4]);
+  g = gemm_args(w.dz2H, H, 0, P + off[3], H, 1, B, H, H);
+  g.mask = w.h1; g.ldm = H; g.outF = w.dz1F; g.ldo = H; g.outH = w.dz1H;
+  g.ldh = H;
+  if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
+  // layer 1: dW1 = x^T dz1, db1 = colsum(dz1), dx = dz1 W1^T
+  g = gemm_args(w.x, CD, 1, w.dz1H, H, 0, CD, H, B);
+  g.outF = G + off[1]; g.ldo = H;
+  if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
+  hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256), dim3(256), 0, st,
+                     w.dz1F, B, H, H, G + off[2]);
+  g = gemm_args(w.dz1H, H, 0, P + off[1], H, 1, B, CD, H);
+  g.outF = w.dxF; g.ldo = CD;
+  if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
+  hipLaunchKernelGGL(embed_scatter_kernel, dim3(V), dim3(64), 0, st, w.dxF,
+                     ids, B, s->context, s->embed, V, G + off[0]);
+  return hipGetLastError() == hipSuccess ? MS_OK : MS_EDEVICE;
+}
+
+ms_status ms_mlp_adam(const ms_mlp_shape* s, float* master, float* m,
+                      float* v, const float* grads, uint16_t* params,
+                      float lr, float beta1, float beta2, float eps,
+                      int32_t step, void* stream) {
+  uint64_t off[7];
+  const uint64_t n = ms_mlp_offsets(s, off);
+  if (!n || !master || !m || !v || !grads || !params || step < 1)
+    return MS_EINVAL;
+  const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, step)));
+  const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, step)));
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), master, m, v, grads,
+                     params, n, lr, beta1, beta2, eps, c1, c2);
+  return hipGetLastError() == hipSuccess ? MS_OK : MS_EDEVICE;
+}
+
+ms_status ms_mlp_to_bf16(const float* src, uint16_t* dst, uint64_t n,
+                         void* stream) {
+  if (!src || !dst) return MS_EINVAL;
+  if (!n) return MS_OK;
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), src, dst, n);
+  return hipGetLastError() == hipSuccess ? MS_OK : MS_EDEVICE;
+}
+
+ms_status ms_mlp_topk(const float* logits, int32_t batch, int32_t vocab,
+                      int32_t k, int32_t exclude, int32_t* out_ids,
+                      void* stream) {
+  if (!logits || !out_ids || batch < 1 || vocab < 1 || k < 1 || k > 16 ||
+      k > vocab - (exclude >= 0 && exclude < vocab ? 1 : 0))
+    return MS_EINVAL;
+  hipLaunchKernelGGL(topk_kernel, dim3(batch), dim3(64), 0,
+                     static_cast<hipStream_t>(stream), logits, vocab, k,
+                     exclude, out_ids);
+  return hipGetLastError() == hipSuccess ? MS_OK : MS_EDEVICE;
+}
+
+}  // extern "C"

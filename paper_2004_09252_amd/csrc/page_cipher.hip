@@ -431,15 +431,15 @@ struct BatchStream {
 };
 
 template <int ROUNDS, int UNROLL>
-__global__ __launch_bounds__(kBlockThreads, UNROLL == 2 ? 7 : 8) void batch_pages_kernel(
-    const DevBatchHdr* __restrict__ hdr, const uint32_t* __restrict__ keys,
-    uint32_t pages_per_wave) {
-  __shared__ uint4 lds[kWavesPerBlock][256];
+__device__ __forceinline__ void batch_body(const DevBatchHdr* hdr,
+                                           const DevReq* reqs,
+                                           const uint32_t* keys,
+                                           uint32_t pages_per_wave,
+                                           uint4* lds, uint32_t w) {
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint32_t w = wave_in_block();
   const uint64_t wave = (uint64_t)blockIdx.x * kWavesPerBlock + w;
   BatchStream s;
-  s.b.reqs = reinterpret_cast<const DevReq*>(hdr + 1);
+  s.b.reqs = reqs;
   s.b.keys = keys;
   s.b.total = cnst(hdr)->total_pages;
   s.b.n_req = cnst(hdr)->n_req;
@@ -448,7 +448,29 @@ __global__ __launch_bounds__(kBlockThreads, UNROLL == 2 ? 7 : 8) void batch_page
   s.c0 = wave * pages_per_wave;
   if (s.c0 >= s.b.total) return;
   s.b.start_chunk(s.c0);
-  run_pages<ROUNDS, UNROLL>(s, lds[w], lane);
+  run_pages<ROUNDS, UNROLL>(s, lds, lane);
+}
+
+// Descriptors in device memory (copied there before the launch).
+template <int ROUNDS, int UNROLL>
+__global__ __launch_bounds__(kBlockThreads, UNROLL == 2 ? 7 : 8) void batch_pages_kernel(
+    const DevBatchHdr* __restrict__ hdr, const uint32_t* __restrict__ keys,
+    uint32_t pages_per_wave) {
+  __shared__ uint4 lds[kWavesPerBlock][256];
+  const uint32_t w = wave_in_block();
+  batch_body<ROUNDS, UNROLL>(hdr, reinterpret_cast<const DevReq*>(hdr + 1),
+                             keys, pages_per_wave, lds[w], w);
+}
+
+// Small batches: descriptors travel inside the kernel arguments, so the
+// launch needs no separate host-to-device copy.
+template <int ROUNDS, int UNROLL>
+__global__ __launch_bounds__(kBlockThreads, UNROLL == 2 ? 7 : 8) void batch_inline_kernel(
+    InlineBatch b, const uint32_t* __restrict__ keys,
+    uint32_t pages_per_wave) {
+  __shared__ uint4 lds[kWavesPerBlock][256];
+  const uint32_t w = wave_in_block();
+  batch_body<ROUNDS, UNROLL>(&b.hdr, b.req, keys, pages_per_wave, lds[w], w);
 }
 
 // --------------------------------------------------------------- probes ---
@@ -620,6 +642,35 @@ hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
   void* args[] = {(void*)&batch, (void*)&keys, (void*)&pages_per_wave};
   return hipLaunchKernel(fn, dim3(grid_blocks), dim3(kBlockThreads), args, 0,
                          stream);
+}
+
+hipError_t launch_batch_inline(const InlineBatch& b, const uint32_t* keys,
+                               uint32_t pages_per_wave, uint32_t unroll,
+                               uint32_t grid_blocks, int rounds,
+                               hipStream_t stream) {
+  if (pages_per_wave == 0 || grid_blocks == 0 || b.hdr.n_req == 0 ||
+      b.hdr.n_req > kInlineReqs)
+    return hipErrorInvalidValue;
+#define MS_INLINE(R, U)                                                     \
+  hipLaunchKernelGGL((batch_inline_kernel<R, U>), dim3(grid_blocks),       \
+                     dim3(kBlockThreads), 0, stream, b, keys, pages_per_wave)
+  if (unroll == 2) {
+    switch (rounds) {
+      case 20: MS_INLINE(20, 2); break;
+      case 12: MS_INLINE(12, 2); break;
+      case 8: MS_INLINE(8, 2); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (rounds) {
+      case 20: MS_INLINE(20, 1); break;
+      case 12: MS_INLINE(12, 1); break;
+      case 8: MS_INLINE(8, 1); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef MS_INLINE
+  return hipGetLastError();
 }
 
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes,

@@ -107,6 +107,11 @@ class ms_serve_result(ctypes.Structure):
         [("reserved", ctypes.c_uint64 * 4)]
 
 
+class ms_mlp_shape(ctypes.Structure):
+    _fields_ = [("vocab", ctypes.c_int32), ("context", ctypes.c_int32),
+                ("embed", ctypes.c_int32), ("hidden", ctypes.c_int32)]
+
+
 _lib = None
 _lib_lock = threading.Lock()
 
@@ -145,6 +150,18 @@ _SIGS = {
     "ms_probe_copy": ([_P, _P, _P, _U64, _U32, _P], _I32),
     "ms_probe_valu": ([_P, _P, _U32, _U32, _P, ctypes.POINTER(_U64)], _I32),
     "ms_device_cu_count": ([_P], ctypes.c_int),
+    "ms_mlp_offsets": ([ctypes.POINTER(ms_mlp_shape), ctypes.POINTER(_U64)],
+                       _U64),
+    "ms_mlp_workspace_bytes": ([ctypes.POINTER(ms_mlp_shape), _I32], _U64),
+    "ms_mlp_forward": ([ctypes.POINTER(ms_mlp_shape), _P, _P, _I32, _P, _P,
+                        _U64, _P], _I32),
+    "ms_mlp_backward": ([ctypes.POINTER(ms_mlp_shape), _P, _P, _P, _I32, _P,
+                         _P, _P, _U64, _P], _I32),
+    "ms_mlp_adam": ([ctypes.POINTER(ms_mlp_shape), _P, _P, _P, _P, _P,
+                     ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                     ctypes.c_float, _I32, _P], _I32),
+    "ms_mlp_to_bf16": ([_P, _P, _U64, _P], _I32),
+    "ms_mlp_topk": ([_P, _I32, _I32, _I32, _I32, _P, _P], _I32),
     "ms_serve_run": ([_P, ctypes.POINTER(ms_serve_trace),
                       ctypes.POINTER(_U64), _U32, _P, _U64, _P, _U64, _I32,
                       _U32, _P, ctypes.POINTER(ms_serve_result)], _I32),
@@ -326,6 +343,42 @@ def ms_serve_run(ctx, trace: ms_serve_trace, keys, src_pool, src_pages,
                            src_pages, dst_pool, dst_pages, mode,
                            submit_threads, lat, ctypes.byref(res))
     return st, res
+
+
+def ms_mlp_offsets(shape: ms_mlp_shape):
+    off = (ctypes.c_uint64 * 7)()
+    total = _L().ms_mlp_offsets(ctypes.byref(shape), off)
+    return total, list(off)
+
+
+def ms_mlp_workspace_bytes(shape: ms_mlp_shape, max_batch: int) -> int:
+    return _L().ms_mlp_workspace_bytes(ctypes.byref(shape), max_batch)
+
+
+def ms_mlp_forward(shape, params, ids, batch, logits, ws, ws_bytes,
+                   stream=None) -> int:
+    return _L().ms_mlp_forward(ctypes.byref(shape), params, ids, batch, logits,
+                               ws, ws_bytes, stream)
+
+
+def ms_mlp_backward(shape, params, ids, targets, batch, grads, loss, ws,
+                    ws_bytes, stream=None) -> int:
+    return _L().ms_mlp_backward(ctypes.byref(shape), params, ids, targets,
+                                batch, grads, loss, ws, ws_bytes, stream)
+
+
+def ms_mlp_adam(shape, master, m, v, grads, params, lr, beta1, beta2, eps,
+                step, stream=None) -> int:
+    return _L().ms_mlp_adam(ctypes.byref(shape), master, m, v, grads, params,
+                            lr, beta1, beta2, eps, step, stream)
+
+
+def ms_mlp_to_bf16(src, dst, n, stream=None) -> int:
+    return _L().ms_mlp_to_bf16(src, dst, n, stream)
+
+
+def ms_mlp_topk(logits, batch, vocab, k, exclude, out_ids, stream=None) -> int:
+    return _L().ms_mlp_topk(logits, batch, vocab, k, exclude, out_ids, stream)
 
 
 # ---- convenience wrapper over torch tensors ----

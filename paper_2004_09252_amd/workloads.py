@@ -137,3 +137,74 @@ def serving(seed: int = 4, rate_hz: float = 20000.0, duration_s: float = 10.0,
     va = (VA_BASE + PAGE * rng.integers(0, 1 << 24, size=n)).astype(np.int64)
     pid = (1000 + clients).astype(np.int64)
     return Serving(keys, t, clients, ops, pages, src, pid, va)
+
+
+@dataclasses.dataclass
+class AccessTrace:
+    """Page accesses of several clients.  Client c owns pages
+    [0, pages_per_client) of its own address space (virtual address
+    VA_BASE + 4096*page, PID 1000 + c).  Access t of client c touches
+    page[c][t]; when value[c][t] != 0 it is a write that XORs the 64-bit
+    value into 8-byte word word[c][t] of the page."""
+    pages_per_client: int
+    page: np.ndarray      # (clients, steps) int32
+    word: np.ndarray      # (clients, steps) int16
+    value: np.ndarray     # (clients, steps) uint64, 0 = read
+    kind: np.ndarray      # (clients, steps) int8: 0 scan1, 1 scank, 2 zipf, 3 loop
+
+    @property
+    def clients(self) -> int:
+        return self.page.shape[0]
+
+    @property
+    def steps(self) -> int:
+        return self.page.shape[1]
+
+
+def _segment(rng, kind, length, n, perm, zipf_p):
+    if kind == 0:        # stride-1 scan
+        s = rng.integers(0, n)
+        return (s + np.arange(length)) % n
+    if kind == 1:        # stride-k scan
+        k = int(rng.choice([2, 4, 8, 16, 64]))
+        s = rng.integers(0, n)
+        return (s + k * np.arange(length)) % n
+    if kind == 2:        # Zipf(1.1) over a fixed permutation of the pages
+        ranks = rng.choice(n, size=length, p=zipf_p)
+        return perm[ranks]
+    loop_len = min(512, n)  # a 512-page sequence repeated
+    s = rng.integers(0, n)
+    seq = (s + np.arange(loop_len)) % n
+    return np.resize(seq, length)
+
+
+def access_trace(seed: int = 5, total_pages: int = 65536,
+                 accesses: int = 2_000_000, clients: int = 64,
+                 mean_segment: int = 2048, write_fraction: float = 0.25,
+                 zipf_alpha: float = 1.1) -> AccessTrace:
+    """Segments of geometric length (mean `mean_segment`), each one of: a
+    stride-1 scan, a stride-k scan (k in {2, 4, 8, 16, 64}), Zipf(alpha)
+    random accesses over a fixed random permutation of the client's pages,
+    or a 512-page loop; chosen uniformly."""
+    rng = np.random.default_rng(seed)
+    n = total_pages // clients
+    steps = accesses // clients
+    ranks = np.arange(1, n + 1, dtype=np.float64)
+    zipf_p = ranks ** (-zipf_alpha)
+    zipf_p /= zipf_p.sum()
+    page = np.empty((clients, steps), dtype=np.int32)
+    kind = np.empty((clients, steps), dtype=np.int8)
+    for c in range(clients):
+        perm = rng.permutation(n)
+        t = 0
+        while t < steps:
+            length = min(int(rng.geometric(1.0 / mean_segment)), steps - t)
+            k = int(rng.integers(0, 4))
+            page[c, t:t + length] = _segment(rng, k, length, n, perm, zipf_p)
+            kind[c, t:t + length] = k
+            t += length
+    word = rng.integers(0, 512, size=(clients, steps)).astype(np.int16)
+    is_write = rng.random((clients, steps)) < write_fraction
+    value = rng.integers(1, 2**63, size=(clients, steps), dtype=np.uint64)
+    value[~is_write] = 0
+    return AccessTrace(n, page, word, value, kind)

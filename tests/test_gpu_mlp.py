@@ -1,0 +1,139 @@
+"""GPU predictor kernels vs the float64 reference network fed the same
+bf16-rounded tensors (oracle/mlp_ref.py).  Tolerance for float32-accumulated
+bf16 products against the float64 reference, per tensor: max|diff| <=
+2^-6 * max|ref| and cosine similarity >= 0.999.  Integer decisions (top-k)
+are compared exactly, both sides deciding on the GPU's own float32 logits."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = dict(vocab=1024, context=16, embed=64, hidden=256)
+
+
+def _note(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def _close(got, ref, what):
+    got = np.asarray(got, dtype=np.float64).reshape(-1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1)
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref))
+    cos = float(got @ ref / (np.linalg.norm(got) * np.linalg.norm(ref) +
+                             1e-300))
+    assert err <= 2**-6 * scale, "%s: max err %g vs scale %g" % (what, err,
+                                                                   scale)
+    assert cos >= 0.999, "%s: cosine %f" % (what, cos)
+
+
+@pytest.fixture(scope="module")
+def pred():
+    from paper_2004_09252_amd.predictor import Predictor
+    return Predictor(max_batch=1024, **SHAPE)
+
+
+def _load(pred, seed):
+    rng = np.random.default_rng(seed)
+    p = mlp_ref.init_params(rng, **SHAPE)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.normal(0, 0.1, p[k].shape)
+    blob = np.concatenate([p[k].reshape(-1) for k in mlp_ref.PARAMS])
+    pred.load_master(blob.astype(np.float32))
+    pb = {k: mlp_ref.bf16_round(v.astype(np.float32)) for k, v in p.items()}
+    return pb, rng
+
+
+def test_bf16_blob_is_round_to_nearest_even(pred):
+    _note("bf16 blob")
+    import torch
+    _load(pred, 1)
+    want = pred.master.cpu().to(torch.bfloat16)
+    assert torch.equal(pred.params.cpu().view(torch.int16),
+                       want.view(torch.int16))
+
+
+@pytest.mark.parametrize("batch", [1, 7, 64, 200, 1024])
+def test_forward_matches_reference(pred, batch):
+    _note("forward batch=%d" % batch)
+    pb, rng = _load(pred, 2)
+    ids = rng.integers(0, SHAPE["vocab"], size=(batch, SHAPE["context"]))
+    got = pred.forward(ids).cpu().numpy()
+    ref, _ = mlp_ref.forward(pb, ids, round_fn=mlp_ref.bf16_round)
+    _close(got, ref, "logits")
+
+
+def test_backward_matches_reference(pred):
+    _note("backward")
+    pb, rng = _load(pred, 3)
+    B = 1024
+    ids = rng.integers(0, SHAPE["vocab"], size=(B, SHAPE["context"]))
+    # skewed ids so that embedding rows collect many contributions
+    ids[: B // 2] = rng.integers(0, 8, size=(B // 2, SHAPE["context"]))
+    tgt = rng.integers(0, SHAPE["vocab"], size=B)
+    loss = float(pred.backward(ids, tgt).cpu().numpy()[0])
+    ref_loss, g = mlp_ref.loss_and_grads(pb, ids, tgt,
+                                         round_fn=mlp_ref.bf16_round,
+                                         grad_round_fn=mlp_ref.bf16_round)
+    assert abs(loss - ref_loss) <= 1e-3 * abs(ref_loss)
+    gg = pred.unpack(pred.grads.cpu())
+    for k in mlp_ref.PARAMS:
+        _close(gg[k].numpy(), g[k], "grad " + k)
+
+
+def test_adam_step_matches_reference(pred):
+    _note("adam")
+    import torch
+    _load(pred, 4)
+    rng = np.random.default_rng(44)
+    g = rng.normal(0, 1e-2, pred.n_params).astype(np.float32)
+    w0 = pred.master.cpu().numpy().astype(np.float64)
+    pred.grads.copy_(torch.from_numpy(g))
+    for _ in range(3):
+        pred.adam(lr=1e-3)
+    got = pred.master.cpu().numpy()
+    p = {"w": w0.copy()}
+    m = {"w": np.zeros_like(w0)}
+    v = {"w": np.zeros_like(w0)}
+    for t in range(1, 4):
+        m["w"] = 0.9 * m["w"] + 0.1 * g
+        v["w"] = 0.999 * v["w"] + 0.001 * g.astype(np.float64) ** 2
+        p["w"] = p["w"] - 1e-3 * (m["w"] / (1 - 0.9 ** t)) / (
+            np.sqrt(v["w"] / (1 - 0.999 ** t)) + 1e-8)
+    assert np.max(np.abs(got - p["w"])) < 1e-6
+    want = pred.master.cpu().to(torch.bfloat16)
+    assert torch.equal(pred.params.cpu().view(torch.int16),
+                       want.view(torch.int16))
+
+
+def test_topk_exact_on_gpu_logits(pred):
+    _note("topk")
+    pb, rng = _load(pred, 5)
+    ids = rng.integers(0, SHAPE["vocab"], size=(300, SHAPE["context"]))
+    logits = pred.forward(ids)
+    host = logits.cpu().numpy()
+    # plant ties
+    host[0, 10] = host[0, 20] = host[0, 30] = host[0].max() + 1.0
+    logits.copy_(__import__("torch").from_numpy(host))
+    got = pred.topk(logits, 8, SHAPE["vocab"] - 1).cpu().numpy()
+    want = mlp_ref.topk_ids(host, 8, exclude=SHAPE["vocab"] - 1)
+    assert np.array_equal(got, want)
+    assert got[0, :3].tolist() == [10, 20, 30]
+
+
+def test_training_learns_a_simple_rule(pred):
+    """Target = the last input id: the loss must fall far below log(V)."""
+    _note("training")
+    _load(pred, 6)
+    rng = np.random.default_rng(66)
+    from paper_2004_09252_amd import prefetch
+    xs = rng.integers(0, 64, size=(8192, SHAPE["context"])).astype(np.int32)
+    ys = xs[:, -1].copy()
+    losses = prefetch.train(pred, xs, ys, steps=300, batch=256, lr=3e-3)
+    assert losses[0] > 5.0
+    assert losses[-20:].mean() < 0.5, losses[-20:]

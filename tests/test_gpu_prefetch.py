@@ -1,0 +1,115 @@
+"""The decrypt-on-fault simulation with its page data on the GPU, with and
+without the learned predictor: counters equal the reference model's, and
+the ciphertext store at the end is bit-exact against the oracle (every
+touched page = ChaCha20 of its final plaintext under its client's key and
+the page's (virtual address, PID) nonce)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import window_sim
+from paper_2004_09252_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+HOST_THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _note(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def _keys(tr, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.bytes(32) for _ in range(tr.clients)]
+
+
+def _check_store(mem, tr, key_bytes, stop):
+    n = tr.pages_per_client
+    store = mem.store.cpu().numpy().reshape(tr.clients, n, 4096)
+    for c in range(tr.clients):
+        plain = window_sim.final_plaintext(n, tr.page[c, :stop],
+                                           tr.word[c, :stop],
+                                           tr.value[c, :stop])
+        touched = np.zeros(n, bool)
+        touched[np.unique(tr.page[c, :stop])] = True
+        nonces = oracle.nonces_linear(n, workloads.VA_BASE, 4096, 1000 + c)
+        want = oracle.cipher_pages(key_bytes[c], nonces, plain,
+                                   threads=HOST_THREADS)
+        assert np.array_equal(store[c][touched], want[touched]), \
+            "client %d ciphertext store" % c
+        assert not store[c][~touched].any()
+
+
+def _oracle_counts(tr, window, start, stop, decisions=None, slots=0):
+    tot = {}
+    for c in range(tr.clients):
+        pf = None
+        if decisions is not None:
+            pf = {t: q for (cc, t), q in decisions.items() if cc == c}
+        o, _ = window_sim.simulate(tr.page[c, :stop], window, prefetch=pf,
+                                   prefetch_slots=slots, start=start)
+        for k, v in o.items():
+            tot[k] = tot.get(k, 0) + v
+    return tot
+
+
+def test_baseline_store_bit_exact():
+    _note("prefetch baseline")
+    from paper_2004_09252_amd import memshield as ms
+    from paper_2004_09252_amd import prefetch
+    tr = workloads.access_trace(seed=21, total_pages=16 * 256,
+                                accesses=16 * 1500, clients=16)
+    kb = _keys(tr, 21)
+    eng = ms.Engine(0)
+    try:
+        keys = [eng.key_load(k) for k in kb]
+        mem = prefetch.PagedMemory(eng, keys, tr.pages_per_client, slots=40)
+        cnt, _, _, cl = prefetch.run(tr, 6, mem=mem)
+        prefetch.finish(mem, cl)
+        ref = _oracle_counts(tr, 6, 0, tr.steps)
+        for k, v in ref.items():
+            assert cnt[k] == v, k
+        assert mem.launches < cnt["decrypts"] + cnt["encrypts"]
+        _check_store(mem, tr, kb, tr.steps)
+    finally:
+        eng.close()
+
+
+def test_predictor_run_counts_and_store_bit_exact():
+    """Train briefly on the fault events of the first 60% and prefetch in
+    the rest; the oracle replays the same prefetch decisions."""
+    _note("prefetch with predictor")
+    from paper_2004_09252_amd import memshield as ms
+    from paper_2004_09252_amd import prefetch
+    from paper_2004_09252_amd.predictor import Predictor
+    tr = workloads.access_trace(seed=22, total_pages=16 * 256,
+                                accesses=16 * 3000, clients=16)
+    kb = _keys(tr, 22)
+    W, P = 6, 8
+    split = int(tr.steps * 0.6)
+    _, events, _, _ = prefetch.run(tr, W, stop=split, record_events=True)
+    vocab = prefetch.DeltaVocab([d for ev in events for d in np.diff(ev)])
+    xs, ys = prefetch.training_examples(events, vocab, 16)
+    pred = Predictor(max_batch=1024)
+    prefetch.train(pred, xs, ys, steps=150, batch=512, lr=2e-3)
+    eng = ms.Engine(0)
+    try:
+        keys = [eng.key_load(k) for k in kb]
+        mem = prefetch.PagedMemory(eng, keys, tr.pages_per_client,
+                                   slots=W + P + 24)
+        cnt, _, dec, cl = prefetch.run(tr, W, mem=mem, prefetch_slots=P,
+                                       predictor=pred, vocab=vocab, k=8,
+                                       predict_from=split, count_from=split)
+        prefetch.finish(mem, cl)
+        ref = _oracle_counts(tr, W, split, tr.steps, decisions=dec, slots=P)
+        for k, v in ref.items():
+            assert cnt[k] == v, k
+        assert cnt["prefetch_issued"] > 0 and cnt["prefetch_hits"] > 0
+        _check_store(mem, tr, kb, tr.steps)
+    finally:
+        eng.close()

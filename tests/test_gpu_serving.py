@@ -119,34 +119,40 @@ def test_alone_equals_mix_equals_oracle(ms):
 
 
 def test_batches_overlap_on_device(ms):
-    """A request that arrives while another batch runs is launched as its own
-    batch on another stream before the first finishes."""
+    """Requests that arrive while a large batch runs are launched as their
+    own batches on other streams and complete before the large one."""
     _note("overlap")
     eng = ms.Engine(0)
     try:
-        r = _Reqs(ms, eng, seed=42, n=2, max_pages=2)
+        r = _Reqs(ms, eng, seed=42, n=8, max_pages=2)
         import torch
+        # warm up: kernels loaded, streams created
+        t = eng.submit([r.req(7, r.dst_b)])
+        assert eng.poll(t, timeout_s=30)[0] == 0
         big_pages = 65536
         big = torch.zeros(big_pages * 4096, dtype=torch.uint8, device="cuda")
-        # a narrow grid for the big request leaves room on the chip
+        # a narrow grid for the large request leaves room on the chip
         assert ms.ms_set_tuning(eng.ctx, ms.ms_tuning(64, 1, 2, 0, 0.0)) == 0
-        k = r.keys[0]
-        tb = eng.submit([ms.request(k, big, big, big_pages,
+        before = eng.stats().batches
+        tb = eng.submit([ms.request(r.keys[0], big, big, big_pages,
                                     ms.linear_nonce(0, 1, 0))])
         t0 = time.time()
-        while eng.stats().batches < 1 and time.time() - t0 < 10:
+        while eng.stats().batches == before and time.time() - t0 < 10:
             pass
-        ts = eng.submit([r.req(0, r.dst_a)])
-        st, d_small = eng.poll(ts, timeout_s=30)
-        assert st == 0 and d_small == [1]
-        st2, d_big = eng.poll(tb, timeout_s=0)
+        overlapped = 0
+        for i in range(6):
+            ts = eng.submit([r.req(i, r.dst_a)])
+            st, d_small = eng.poll(ts, timeout_s=30)
+            assert st == 0 and d_small == [1]
+            st2, d_big = eng.poll(tb, timeout_s=0)
+            overlapped += d_big == [0]
         stats = eng.stats()
         st, _ = eng.poll(tb, timeout_s=30)
         assert st == 0
         assert stats.max_inflight_batches >= 2
-        # the small request finished while the big one was still running
-        assert d_big == [0], "big request finished first: no overlap shown"
-        assert np.array_equal(r.slice(r.dst_a, 0), r.expect(0))
+        assert overlapped >= 1, "no small request finished during the big one"
+        for i in range(6):
+            assert np.array_equal(r.slice(r.dst_a, i), r.expect(i))
     finally:
         ms.ms_set_tuning(eng.ctx, None)
         eng.close()
