@@ -348,6 +348,101 @@ def run_serving(args, ms, torch):
     return out
 
 
+def run_prefetch(args, ms, torch):
+    """Learned pre-decryption on the 2M-access trace (64 clients x 1024
+    pages): train on the fault events of the first 80%, then compare, over
+    the last 20%, decrypt-on-fault with a window of W+P pages against a
+    window of W pages plus P pre-decrypted pages chosen by the predictor.
+    Both runs move every page through the GPU; the final ciphertext stores
+    are checked against the oracle."""
+    import numpy as np
+    import oracle
+    from oracle import window_sim
+    from paper_2004_09252_amd import prefetch, workloads
+    from paper_2004_09252_amd.predictor import Predictor
+    W, P = args.prefetch_window, 8
+    tr = workloads.access_trace(seed=5)
+    split = int(tr.steps * 0.8)
+    t0 = time.perf_counter()
+    _, events, _, _ = prefetch.run(tr, W, stop=split, record_events=True)
+    vocab = prefetch.DeltaVocab([d for ev in events for d in np.diff(ev)])
+    xs, ys = prefetch.training_examples(events, vocab, 16)
+    t_events = time.perf_counter() - t0
+    pred = Predictor(max_batch=1024, seed=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = prefetch.train(pred, xs, ys, steps=args.prefetch_train_steps,
+                            batch=1024, lr=1e-3, seed=5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    rng = np.random.default_rng(5)
+    kb = [rng.bytes(32) for _ in range(tr.clients)]
+    eng = ms.Engine(0, max_keys=128)
+    keys = [eng.key_load(k) for k in kb]
+    out = {"workload": "64 clients x 1024 pages (65536 pages), %d accesses, "
+                       "train on the first 80%%, evaluate the last 20%%"
+                       % (tr.clients * tr.steps),
+           "window": W, "prefetch_slots": P, "k": 8,
+           "train": {"examples": int(xs.shape[0]),
+                     "steps": args.prefetch_train_steps, "batch": 1024,
+                     "loss_first": round(float(losses[0]), 4),
+                     "loss_last": round(float(losses[-50:].mean()), 4),
+                     "seconds": round(t_train, 2),
+                     "event_pass_seconds": round(t_events, 2)}}
+    plain = [window_sim.final_plaintext(tr.pages_per_client, tr.page[c],
+                                        tr.word[c], tr.value[c])
+             for c in range(tr.clients)]
+
+    def store_ok(mem):
+        n = tr.pages_per_client
+        st = mem.store.cpu().numpy().reshape(tr.clients, n, 4096)
+        for c in range(tr.clients):
+            touched = np.zeros(n, bool)
+            touched[np.unique(tr.page[c])] = True
+            nonces = oracle.nonces_linear(n, workloads.VA_BASE, 4096,
+                                          1000 + c)
+            want = oracle.cipher_pages(kb[c], nonces, plain[c], threads=16)
+            if not np.array_equal(st[c][touched], want[touched]):
+                return False
+        return True
+
+    for name, window, slots, use in (("baseline_window_W_plus_P", W + P, 0,
+                                      False),
+                                     ("predictor_window_W_prefetch_P", W, P,
+                                      True)):
+        log("prefetch run: %s" % name)
+        mem = prefetch.PagedMemory(eng, keys, tr.pages_per_client,
+                                   slots=W + P + 32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cnt, _, dec, cl = prefetch.run(
+            tr, window, mem=mem, prefetch_slots=slots,
+            predictor=pred if use else None, vocab=vocab if use else None,
+            k=8, predict_from=split, count_from=split)
+        prefetch.finish(mem, cl)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        r = dict(cnt)
+        r["decrypt_fault_rate"] = round(cnt["faults"] / cnt["accesses"], 5)
+        if use:
+            r["prefetch_precision"] = round(
+                cnt["prefetch_hits"] / max(cnt["prefetch_issued"], 1), 4)
+        r["seconds"] = round(dt, 2)
+        r["fused_launches"] = mem.launches
+        r["pages_through_gpu"] = mem.pages_moved
+        r["ciphertext_store_bit_exact"] = store_ok(mem)
+        out[name] = r
+        del mem
+        torch.cuda.empty_cache()
+    b = out["baseline_window_W_plus_P"]["faults"]
+    p = out["predictor_window_W_prefetch_P"]["faults"]
+    out["decrypt_faults_removed_frac"] = round(1 - p / max(b, 1), 4)
+    for k in keys:
+        eng.key_destroy(k)
+    eng.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -364,6 +459,9 @@ def main():
     ap.add_argument("--sweep-rates", type=float, nargs="*",
                     default=[20000, 50000, 100000, 200000, 400000])
     ap.add_argument("--sweep-duration", type=float, default=1.0)
+    ap.add_argument("--no-prefetch", action="store_true")
+    ap.add_argument("--prefetch-window", type=int, default=8)
+    ap.add_argument("--prefetch-train-steps", type=int, default=1500)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the page cipher needs no "
@@ -430,6 +528,8 @@ def main():
         line["batched"] = run_batched(args, ms, torch)
     if not args.no_serving:
         line["serving"] = run_serving(args, ms, torch)
+    if not args.no_prefetch:
+        line["learned_prefetch"] = run_prefetch(args, ms, torch)
     if not args.no_cpu_baseline:
         sp = min(args.cpu_sample_pages, n)
         log("cpu baseline on %d pages" % sp)

@@ -99,10 +99,9 @@ def final_plaintext(n_pages: int, pages, words, values) -> np.ndarray:
     """(n_pages, 4096) uint8: every page starts as zeros (first touch) and
     each access with a non-zero value XORs it into 8-byte word `words[t]`."""
     mem = np.zeros((n_pages, 512), dtype=np.uint64)
-    for p, w, v in zip(pages, words, values):
-        v = int(v)
-        if v:
-            mem[int(p), int(w)] ^= np.uint64(v)
+    np.bitwise_xor.at(mem, (np.asarray(pages, dtype=np.int64),
+                            np.asarray(words, dtype=np.int64)),
+                      np.asarray(values, dtype=np.uint64))
     return mem.astype("<u8").view(np.uint8).reshape(n_pages, 4096)
 
 

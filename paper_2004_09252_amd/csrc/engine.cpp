@@ -538,20 +538,7 @@ bool launch_one(ms_ctx* c) {
   c->st_pf_issued.fetch_add(n_pf);
   ms_status st = MS_OK;
   hipStream_t strm = c->serve_streams[stream_i];
-  const uint32_t n_dev = reinterpret_cast<ms::DevBatchHdr*>(s.host)->n_req;
-  if (copy && n_dev <= ms::kInlineReqs) {
-    // small batch: descriptors ride in the kernel arguments, no copy
-    ms::InlineBatch ib;
-    std::memset(&ib, 0, sizeof(ib));
-    std::memcpy(&ib, s.host, copy);
-    const Tuning t = tuning_for(c, total);
-    const uint32_t grid = grid_blocks_for(c, t, total);
-    hipError_t e = ms::launch_batch_inline(ib, c->d_keys, t.ppw, t.unroll,
-                                           grid, (int)c->cfg.rounds, strm);
-    if (hip_ok(e)) e = hipEventRecord(s.done, strm);
-    if (!hip_ok(e)) st = dev_err(c, e);
-    s.used = true;
-  } else if (copy) {
+  if (copy) {
     st = issue_slot(c, s, copy, total, strm, false);
   } else if (!hip_ok(hipEventRecord(s.done, strm))) {
     st = MS_EDEVICE;

@@ -41,13 +41,6 @@ struct DevBatchHdr {
 };
 static_assert(sizeof(DevBatchHdr) == 64, "DevBatchHdr layout");
 
-// A small batch passed by value in the kernel arguments (3136 bytes).
-constexpr uint32_t kInlineReqs = 48;
-struct InlineBatch {
-  DevBatchHdr hdr;
-  DevReq req[kInlineReqs];
-};
-
 // Arguments of one plain launch over a run of pages.
 struct PlainArgs {
   const uint32_t* keys;  // device key table, 8 words per slot
@@ -72,10 +65,6 @@ hipError_t launch_plain(const PlainArgs& a, uint32_t kind, int rounds,
 hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
                         uint32_t pages_per_wave, uint32_t unroll,
                         uint32_t grid_blocks, int rounds, hipStream_t stream);
-hipError_t launch_batch_inline(const InlineBatch& b, const uint32_t* keys,
-                               uint32_t pages_per_wave, uint32_t unroll,
-                               uint32_t grid_blocks, int rounds,
-                               hipStream_t stream);
 // Kernel entry points (graph capture, occupancy queries).
 const void* batch_kernel_fn(uint32_t unroll, int rounds);
 const void* plain_kernel_fn(uint32_t unroll, int rounds, uint32_t kind);

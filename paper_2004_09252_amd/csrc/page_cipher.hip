@@ -169,14 +169,19 @@ __device__ __forceinline__ void keystream(uint32_t (&o)[16],
   o[15] = x15 + n[2];
 }
 
+// Page data always lives in global memory; saying so lets the compiler use
+// global (not flat) loads and stores also where the pointers come from
+// descriptors.
+typedef __attribute__((address_space(1))) v4u gv4u;
+
 __device__ __forceinline__ uint4 load_nt(const uint4* p) {
-  const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
+  const v4u v = __builtin_nontemporal_load((const gv4u*)p);
   return make_uint4(v.x, v.y, v.z, v.w);
 }
 
 __device__ __forceinline__ void store_nt(uint4 a, uint4* p) {
   const v4u v = {a.x, a.y, a.z, a.w};
-  __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(p));
+  __builtin_nontemporal_store(v, (gv4u*)p);
 }
 
 // 16-byte slot i (0..255) of the per-wave keystream buffer, XOR-swizzled so
@@ -462,17 +467,6 @@ __global__ __launch_bounds__(kBlockThreads, UNROLL == 2 ? 7 : 8) void batch_page
                              keys, pages_per_wave, lds[w], w);
 }
 
-// Small batches: descriptors travel inside the kernel arguments, so the
-// launch needs no separate host-to-device copy.
-template <int ROUNDS, int UNROLL>
-__global__ __launch_bounds__(kBlockThreads, UNROLL == 2 ? 7 : 8) void batch_inline_kernel(
-    InlineBatch b, const uint32_t* __restrict__ keys,
-    uint32_t pages_per_wave) {
-  __shared__ uint4 lds[kWavesPerBlock][256];
-  const uint32_t w = wave_in_block();
-  batch_body<ROUNDS, UNROLL>(&b.hdr, b.req, keys, pages_per_wave, lds[w], w);
-}
-
 // --------------------------------------------------------------- probes ---
 
 // Streaming copy: one wave per 4 KiB page, coalesced non-temporal dwordx4
@@ -642,35 +636,6 @@ hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
   void* args[] = {(void*)&batch, (void*)&keys, (void*)&pages_per_wave};
   return hipLaunchKernel(fn, dim3(grid_blocks), dim3(kBlockThreads), args, 0,
                          stream);
-}
-
-hipError_t launch_batch_inline(const InlineBatch& b, const uint32_t* keys,
-                               uint32_t pages_per_wave, uint32_t unroll,
-                               uint32_t grid_blocks, int rounds,
-                               hipStream_t stream) {
-  if (pages_per_wave == 0 || grid_blocks == 0 || b.hdr.n_req == 0 ||
-      b.hdr.n_req > kInlineReqs)
-    return hipErrorInvalidValue;
-#define MS_INLINE(R, U)                                                     \
-  hipLaunchKernelGGL((batch_inline_kernel<R, U>), dim3(grid_blocks),       \
-                     dim3(kBlockThreads), 0, stream, b, keys, pages_per_wave)
-  if (unroll == 2) {
-    switch (rounds) {
-      case 20: MS_INLINE(20, 2); break;
-      case 12: MS_INLINE(12, 2); break;
-      case 8: MS_INLINE(8, 2); break;
-      default: return hipErrorInvalidValue;
-    }
-  } else {
-    switch (rounds) {
-      case 20: MS_INLINE(20, 1); break;
-      case 12: MS_INLINE(12, 1); break;
-      case 8: MS_INLINE(8, 1); break;
-      default: return hipErrorInvalidValue;
-    }
-  }
-#undef MS_INLINE
-  return hipGetLastError();
 }
 
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes,

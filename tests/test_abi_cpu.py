@@ -108,3 +108,28 @@ def test_cipher_kernels_use_no_scratch(tmp_path):
     assert len(names) >= 8 and len(names) == len(scratch)
     bad = [n for n, s in zip(names, scratch) if s != 0]
     assert not bad, bad
+
+
+def test_cipher_kernels_are_not_optimised_away(tmp_path):
+    """Every cipher kernel instantiation must keep its rounds and its
+    stores: a kernel the compiler reduced to an empty body would silently
+    leave its output untouched."""
+    hipcc = "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not present")
+    r = subprocess.run(
+        [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17",
+         "--cuda-device-only", "-S", "-Xclang", "-target-feature", "-Xclang",
+         "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC,
+         os.path.join(CSRC, "page_cipher.hip"), "-o", str(tmp_path / "k.s")],
+        capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    asm = open(tmp_path / "k.s").read()
+    bodies = re.findall(
+        r"^(_Z\S*(?:plain|batch)_pages_kernel\S*):(.*?)^\.Lfunc_end",
+        asm, flags=re.S | re.M)
+    assert len(bodies) >= 18
+    for name, body in bodies:
+        rounds = 20 if "ILi20E" in name else (12 if "ILi12E" in name else 8)
+        assert body.count("v_alignbit_b32") >= 16 * rounds - 40, name
+        assert body.count("global_store_dwordx4") >= 4, name

@@ -293,3 +293,35 @@ def test_loadgen_poisson_sample_exact(ms, mode):
             assert s.batches <= s.submitted
     finally:
         eng.close()
+
+
+@pytest.mark.parametrize("tiling", [None, (8, 1, 28), (1, 1, 1), (8, 2, 28),
+                                    (64, 2, 2)])
+def test_large_submitted_request_every_tiling(ms, tiling):
+    """One request of 65536 pages (256 MiB) through ms_submit, under the
+    default and forced tilings with one and several chunks per wave."""
+    _note("large submit tiling=%s" % (tiling,))
+    import torch
+    eng = ms.Engine(0)
+    try:
+        kb = bytes(range(32))
+        key = eng.key_load(kb)
+        n = 65536
+        g = torch.Generator("cuda").manual_seed(7)
+        src = torch.randint(0, 256, (n * 4096,), dtype=torch.uint8,
+                            device="cuda", generator=g)
+        dst = torch.zeros_like(src)
+        if tiling:
+            assert ms.ms_set_tuning(eng.ctx, ms.ms_tuning(*tiling, 0,
+                                                          0.0)) == 0
+        t = eng.submit([ms.request(key, src, dst, n,
+                                   ms.linear_nonce(7, 4096, 99))])
+        st, d = eng.poll(t, timeout_s=60)
+        assert st == 0 and d == [1]
+        got = dst.cpu().numpy().reshape(n, 4096)
+        want = _oracle_req(kb, 7, 99, src.cpu().numpy()).reshape(n, 4096)
+        bad = np.where(~np.all(got == want, axis=1))[0]
+        assert bad.size == 0, "%d bad pages, first %s" % (bad.size, bad[:5])
+    finally:
+        ms.ms_set_tuning(eng.ctx, None)
+        eng.close()
