@@ -214,7 +214,11 @@ ms_status ms_process_batch(ms_ctx *ctx, const ms_request *reqs, size_t n,
 
 /*
  * Asynchronous serving path (continuous batching).  ms_submit validates the
- * requests and queues them; it never blocks.  A scheduler thread admits queued
+ * requests and queues them; it never blocks.  The engine runs submitted work
+ * on its own streams, which do not wait for the caller's streams: a
+ * request's source bytes (and nonce array) must be complete, and no other
+ * work may still be writing its destination, when ms_submit is called
+ * (e.g. synchronize the stream that produced them first).  A scheduler thread admits queued
  * requests into fused launches while the page bytes in flight stay within
  * admission_cap_bytes and a batch slot is free, so batches that arrive while
  * others run overlap on the device.  tickets_out[i] receives a ticket per

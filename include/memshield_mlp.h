@@ -74,10 +74,12 @@ ms_status ms_mlp_to_bf16(const float *src, uint16_t *dst, uint64_t n,
                          void *stream);
 
 /* Top-k ids of each row of logits[batch][vocab] by value, ties to the lower
- * id, `exclude` (or -1) never chosen; out_ids[batch][k]; k <= 16. */
+ * id, `exclude` (or -1) never chosen; out_ids[batch][k]; k <= 16.  When
+ * out_prob is not NULL it receives the softmax probability of each chosen
+ * id over the whole row (float32, [batch][k]). */
 ms_status ms_mlp_topk(const float *logits, int32_t batch, int32_t vocab,
                       int32_t k, int32_t exclude, int32_t *out_ids,
-                      void *stream);
+                      float *out_prob, void *stream);
 
 #ifdef __cplusplus
 }

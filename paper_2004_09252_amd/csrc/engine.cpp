@@ -538,7 +538,29 @@ bool launch_one(ms_ctx* c) {
   c->st_pf_issued.fetch_add(n_pf);
   ms_status st = MS_OK;
   hipStream_t strm = c->serve_streams[stream_i];
-  if (copy) {
+  if (copy && take.size() == 1) {
+    // a batch of one request needs no descriptors: plain launch
+    const ms_request& r = take[0].req;
+    ms::PlainArgs a;
+    a.keys = c->d_keys;
+    a.src = static_cast<const uint8_t*>(r.src);
+    a.dst = static_cast<uint8_t*>(r.dst);
+    a.nonce_array = reinterpret_cast<const uint32_t*>(r.nonce.array);
+    a.nonce_base = r.nonce.base;
+    a.nonce_stride = r.nonce.stride;
+    a.first_page = 0;
+    a.n_pages = r.n_pages;
+    a.key_slot = ks[0];
+    a.nonce_tag = r.nonce.tag;
+    const Tuning t = plain_tuning(c);
+    hipError_t e = ms::launch_plain(
+        a, r.nonce.kind == MS_NONCE_ARRAY ? ms::kNonceArray : ms::kNonceLinear,
+        (int)c->cfg.rounds, (uint32_t)c->cu_count * t.waves_per_cu, t.unroll,
+        strm);
+    if (hip_ok(e)) e = hipEventRecord(s.done, strm);
+    if (!hip_ok(e)) st = dev_err(c, e);
+    s.used = true;
+  } else if (copy) {
     st = issue_slot(c, s, copy, total, strm, false);
   } else if (!hip_ok(hipEventRecord(s.done, strm))) {
     st = MS_EDEVICE;

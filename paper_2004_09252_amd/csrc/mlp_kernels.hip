@@ -266,13 +266,23 @@ __global__ void to_bf16_kernel(const float* __restrict__ s,
 }
 
 // One wave per row: k rounds of (lane-local best, wave reduction); the
-// order is (value descending, id ascending); NaN counts as -inf.
+// order is (value descending, id ascending); NaN counts as -inf.  With
+// `prob` set, also the softmax probability of each chosen id over the whole
+// row.
 __global__ __launch_bounds__(64) void topk_kernel(
     const float* __restrict__ logits, int V, int k, int exclude,
-    int32_t* __restrict__ out) {
+    int32_t* __restrict__ out, float* __restrict__ prob) {
   const int b = blockIdx.x;
   const int lane = threadIdx.x;
   const float* row = logits + (int64_t)b * V;
+  float mx = -INFINITY, sum = 0.f;
+  if (prob) {
+    for (int i = lane; i < V; i += 64) mx = fmaxf(mx, row[i]);
+    for (int off = 32; off > 0; off >>= 1)
+      mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    for (int i = lane; i < V; i += 64) sum += expf(row[i] - mx);
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+  }
   int chosen[16];
   for (int r = 0; r < k; ++r) {
     float bv = -INFINITY;
@@ -292,7 +302,10 @@ __global__ __launch_bounds__(64) void topk_kernel(
       if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
     }
     chosen[r] = bi;
-    if (lane == 0) out[(int64_t)b * k + r] = bi;
+    if (lane == 0) {
+      out[(int64_t)b * k + r] = bi;
+      if (prob) prob[(int64_t)b * k + r] = expf(bv - mx) / sum;
+    }
   }
 }
 
@@ -496,13 +509,13 @@ ms_status ms_mlp_to_bf16(const float* src, uint16_t* dst, uint64_t n,
 
 ms_status ms_mlp_topk(const float* logits, int32_t batch, int32_t vocab,
                       int32_t k, int32_t exclude, int32_t* out_ids,
-                      void* stream) {
+                      float* out_prob, void* stream) {
   if (!logits || !out_ids || batch < 1 || vocab < 1 || k < 1 || k > 16 ||
       k > vocab - (exclude >= 0 && exclude < vocab ? 1 : 0))
     return MS_EINVAL;
   hipLaunchKernelGGL(topk_kernel, dim3(batch), dim3(64), 0,
                      static_cast<hipStream_t>(stream), logits, vocab, k,
-                     exclude, out_ids);
+                     exclude, out_ids, out_prob);
   return hipGetLastError() == hipSuccess ? MS_OK : MS_EDEVICE;
 }
 

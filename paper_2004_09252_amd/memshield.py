@@ -161,7 +161,7 @@ _SIGS = {
                      ctypes.c_float, ctypes.c_float, ctypes.c_float,
                      ctypes.c_float, _I32, _P], _I32),
     "ms_mlp_to_bf16": ([_P, _P, _U64, _P], _I32),
-    "ms_mlp_topk": ([_P, _I32, _I32, _I32, _I32, _P, _P], _I32),
+    "ms_mlp_topk": ([_P, _I32, _I32, _I32, _I32, _P, _P, _P], _I32),
     "ms_serve_run": ([_P, ctypes.POINTER(ms_serve_trace),
                       ctypes.POINTER(_U64), _U32, _P, _U64, _P, _U64, _I32,
                       _U32, _P, ctypes.POINTER(ms_serve_result)], _I32),
@@ -377,8 +377,10 @@ def ms_mlp_to_bf16(src, dst, n, stream=None) -> int:
     return _L().ms_mlp_to_bf16(src, dst, n, stream)
 
 
-def ms_mlp_topk(logits, batch, vocab, k, exclude, out_ids, stream=None) -> int:
-    return _L().ms_mlp_topk(logits, batch, vocab, k, exclude, out_ids, stream)
+def ms_mlp_topk(logits, batch, vocab, k, exclude, out_ids, out_prob=None,
+                stream=None) -> int:
+    return _L().ms_mlp_topk(logits, batch, vocab, k, exclude, out_ids,
+                            out_prob, stream)
 
 
 # ---- convenience wrapper over torch tensors ----

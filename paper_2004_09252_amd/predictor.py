@@ -41,6 +41,8 @@ class Predictor:
                                   device=device)
         self.topk_out = torch.empty(max_batch * 16, dtype=torch.int32,
                                     device=device)
+        self.topk_prob = torch.empty(max_batch * 16, dtype=torch.float32,
+                                     device=device)
         self.step = 0
         self.init_random(seed)
 
@@ -76,6 +78,21 @@ class Predictor:
         self._check(ms.ms_mlp_to_bf16(self.master.data_ptr(),
                                       self.params.data_ptr(), self.n_params,
                                       self._stream()), "ms_mlp_to_bf16")
+
+    def save(self, path: str) -> None:
+        """Write the float32 master weights and the shape (numpy .npz)."""
+        s = self.shape
+        np.savez(path, master=self.master.cpu().numpy(),
+                 shape=np.array([s.vocab, s.context, s.embed, s.hidden]),
+                 step=np.array([self.step]))
+
+    def load(self, path: str) -> None:
+        """Read weights written by ``save`` (no pickled objects)."""
+        with np.load(path, allow_pickle=False) as z:
+            s = self.shape
+            if z["shape"].tolist() != [s.vocab, s.context, s.embed, s.hidden]:
+                raise ValueError("predictor shape mismatch")
+            self.load_master(z["master"])
 
     def unpack(self, blob: torch.Tensor) -> dict:
         out = {}
@@ -141,12 +158,17 @@ class Predictor:
         self.adam(lr=lr)
         return loss
 
-    def topk(self, logits: torch.Tensor, k: int, exclude: int) -> torch.Tensor:
+    def topk(self, logits: torch.Tensor, k: int, exclude: int,
+             with_prob: bool = False):
         B = logits.shape[0]
         self._check(ms.ms_mlp_topk(logits.data_ptr(), B, self.vocab, k,
                                    exclude, self.topk_out.data_ptr(),
-                                   self._stream()), "ms_mlp_topk")
-        return self.topk_out[:B * k].view(B, k)
+                                   self.topk_prob.data_ptr() if with_prob
+                                   else None, self._stream()), "ms_mlp_topk")
+        ids = self.topk_out[:B * k].view(B, k)
+        if with_prob:
+            return ids, self.topk_prob[:B * k].view(B, k)
+        return ids
 
-    def predict(self, ids, k: int, exclude: int) -> torch.Tensor:
-        return self.topk(self.forward(ids), k, exclude)
+    def predict(self, ids, k: int, exclude: int, with_prob: bool = False):
+        return self.topk(self.forward(ids), k, exclude, with_prob)

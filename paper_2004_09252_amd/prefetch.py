@@ -194,13 +194,15 @@ def new_counters():
 def run(trace, window: int, mem: PagedMemory | None = None,
         prefetch_slots: int = 0, predictor=None, vocab: DeltaVocab | None = None,
         k: int = 8, predict_from: int = 0, stop: int | None = None,
-        count_from: int = 0, record_events: bool = False):
+        count_from: int = 0, record_events: bool = False,
+        min_prob: float = 0.0):
     """Replay `trace` (workloads.AccessTrace) for steps [0, stop) with all
     clients in lockstep.  Prediction is active for steps >= predict_from,
     counters cover steps >= count_from.  Returns (counters, events, decisions)
     where events[c] is the list of fault-event pages of client c (if
     recorded) and decisions maps (c, t) to the pages the predictor asked
-    for after step t."""
+    for after step t.  Of the predictor's top-k deltas only those with a
+    softmax probability of at least `min_prob` are pre-decrypted."""
     C = trace.clients
     n = trace.pages_per_client
     stop = trace.steps if stop is None else stop
@@ -269,13 +271,15 @@ def run(trace, window: int, mem: PagedMemory | None = None,
                             dtype=np.int64)
             ids = vocab.ids(np.diff(hist, axis=1).reshape(-1)).reshape(
                 len(want), ctx)
-            top = predictor.predict(ids, k, vocab.oov).cpu().numpy()
+            top, prob = predictor.predict(ids, k, vocab.oov, with_prob=True)
+            top = top.cpu().numpy()
+            prob = prob.cpu().numpy()
             for row, c in enumerate(want):
                 cl = clients[c]
                 last = int(clients[c].events[-1])
                 asked = []
-                for tid in top[row]:
-                    if int(tid) >= vocab.n_known:
+                for tid, pr in zip(top[row], prob[row]):
+                    if int(tid) >= vocab.n_known or pr < min_prob:
                         continue
                     q = last + int(vocab.delta_of[int(tid)])
                     if not (0 <= q < n) or q in cl.win or q in cl.pf or \

@@ -84,6 +84,7 @@ def run(eng: ms.Engine, lay: Layout, keys, src: torch.Tensor,
     """Run the trace; returns (result struct, latencies in us)."""
     n = lay.trace.n
     lat = np.zeros(n, dtype=np.float64)
+    torch.cuda.synchronize()   # the engine's streams do not wait for torch
     st, res = ms.ms_serve_run(eng.ctx, lay.trace, keys, src.data_ptr(),
                               src.numel() // PAGE, dst.data_ptr(),
                               dst.numel() // PAGE, mode, submit_threads, lat)

@@ -120,10 +120,16 @@ def test_topk_exact_on_gpu_logits(pred):
     # plant ties
     host[0, 10] = host[0, 20] = host[0, 30] = host[0].max() + 1.0
     logits.copy_(__import__("torch").from_numpy(host))
-    got = pred.topk(logits, 8, SHAPE["vocab"] - 1).cpu().numpy()
+    got, prob = pred.topk(logits, 8, SHAPE["vocab"] - 1, with_prob=True)
+    got = got.cpu().numpy()
     want = mlp_ref.topk_ids(host, 8, exclude=SHAPE["vocab"] - 1)
     assert np.array_equal(got, want)
     assert got[0, :3].tolist() == [10, 20, 30]
+    h64 = host.astype(np.float64)
+    sm = np.exp(h64 - h64.max(axis=1, keepdims=True))
+    sm /= sm.sum(axis=1, keepdims=True)
+    want_p = np.take_along_axis(sm, want, axis=1)
+    assert np.max(np.abs(prob.cpu().numpy() - want_p)) < 1e-5
 
 
 def test_training_learns_a_simple_rule(pred):
@@ -137,3 +143,16 @@ def test_training_learns_a_simple_rule(pred):
     losses = prefetch.train(pred, xs, ys, steps=300, batch=256, lr=3e-3)
     assert losses[0] > 5.0
     assert losses[-20:].mean() < 0.5, losses[-20:]
+
+
+def test_save_load_round_trip(pred, tmp_path):
+    _note("save/load")
+    import torch
+    _load(pred, 7)
+    before = pred.params.clone()
+    path = str(tmp_path / "pred.npz")
+    pred.save(path)
+    pred.init_random(123)
+    assert not torch.equal(pred.params, before)
+    pred.load(path)
+    assert torch.equal(pred.params.view(torch.int16), before.view(torch.int16))

@@ -56,6 +56,8 @@ class _Reqs:
         self.src = torch.from_numpy(self.host).to("cuda")
         self.dst_a = torch.zeros_like(self.src)
         self.dst_b = torch.zeros_like(self.src)
+        # submitted work does not wait for torch's stream
+        torch.cuda.synchronize()
         self.ms = ms
 
     def req(self, i, dst):
@@ -131,6 +133,7 @@ def test_batches_overlap_on_device(ms):
         assert eng.poll(t, timeout_s=30)[0] == 0
         big_pages = 65536
         big = torch.zeros(big_pages * 4096, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
         # a narrow grid for the large request leaves room on the chip
         assert ms.ms_set_tuning(eng.ctx, ms.ms_tuning(64, 1, 2, 0, 0.0)) == 0
         before = eng.stats().batches
@@ -174,6 +177,7 @@ def test_admission_cap_bounds_inflight_bytes(ms):
         # a single request larger than the cap can never be admitted
         import torch
         big = torch.zeros(65 * 4096, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
         bad = ms.request(r.keys[0], big, big, 65, ms.linear_nonce(0, 1, 0))
         st, _ = ms.ms_submit(eng.ctx, [bad])
         assert st == ms.MS_EINVAL
@@ -311,6 +315,7 @@ def test_large_submitted_request_every_tiling(ms, tiling):
         src = torch.randint(0, 256, (n * 4096,), dtype=torch.uint8,
                             device="cuda", generator=g)
         dst = torch.zeros_like(src)
+        torch.cuda.synchronize()   # submitted work does not wait for torch
         if tiling:
             assert ms.ms_set_tuning(eng.ctx, ms.ms_tuning(*tiling, 0,
                                                           0.0)) == 0
