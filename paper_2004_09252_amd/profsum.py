@@ -5,6 +5,7 @@ Usage (from the repository root, on the databases a profiling run left):
     python -m paper_2004_09252_amd.profsum trace  <trace.db>  <out.md>  <cmd>
     python -m paper_2004_09252_amd.profsum traffic <fetch.db> <write.db> \
         <out.txt> <cmd-fetch> <cmd-write>
+    python -m paper_2004_09252_amd.profsum valu <valu.db> <out.txt> <cmd>
 
 ``trace`` writes the kernel-trace statistics (rocprofv3 --kernel-trace
 --stats): per kernel and grid size, the number of dispatches and their
@@ -31,6 +32,7 @@ KERNEL_SOURCE = os.path.join(HERE, "csrc", "page_cipher.hip")
 COPY_BYTES = 1 << 30
 BULK_KERNEL = "plain_pages_kernel<20, 2, 1u>"
 COPY_KERNEL = "copy_probe_kernel"
+N_XCD = 8   # GRBM_GUI_ACTIVE comes summed over the 8 XCDs of an MI355X
 
 
 def _short(name: str) -> str:
@@ -125,7 +127,55 @@ def traffic(fetch_db: str, write_db: str, out_path: str, cmd_f: str,
         fo.write("\n".join(lines) + "\n")
 
 
+def valu(db_path: str, out_path: str, cmd: str) -> None:
+    """VALU counters of the bulk plain kernel: VALUBusy (rocprofv3's derived
+    metric: SQ_ACTIVE_INST_VALU / CUs / GRBM_GUI_ACTIVE), vector
+    instructions issued per page, and the effective shader clock
+    (GRBM_GUI_ACTIVE cycles over the dispatch duration)."""
+    db = sqlite3.connect(db_path)
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for name, counter, value, dur in db.execute(
+            "select kernel_name, counter_name, value, duration from "
+            "counters_collection"):
+        if BULK_KERNEL in name:
+            vals[counter]["v"].append(value)
+            vals[counter]["d"].append(dur)
+    pages = 262144
+
+    def avg(c):
+        v = vals[c]["v"]
+        return sum(v) / len(v) if v else float("nan")
+
+    durs = vals["GRBM_GUI_ACTIVE"]["d"]
+    dur = sum(durs) / len(durs) if durs else float("nan")
+    lines = ["# VALU counters of the bulk plain page kernel (1 GiB pass, "
+             "262144 pages)",
+             "# command: " + cmd,
+             "kernel: %s" % BULK_KERNEL,
+             "dispatches: %d" % len(vals["SQ_INSTS_VALU"]["v"]),
+             "VALUBusy_percent: %.2f" % avg("VALUBusy"),
+             "SQ_INSTS_VALU_per_launch: %.0f" % avg("SQ_INSTS_VALU"),
+             "SQ_INSTS_VALU_per_page: %.1f" % (avg("SQ_INSTS_VALU") / pages),
+             "SQ_INSTS_VALU_INT32_per_page: %.1f" % (
+                 avg("SQ_INSTS_VALU_INT32") / pages),
+             "algorithmic_int_ops_per_page_per_lane: %d" % (992),
+             "GRBM_GUI_ACTIVE_cycles_sum_over_%d_xcds: %.0f" % (
+                 N_XCD, avg("GRBM_GUI_ACTIVE")),
+             "dispatch_duration_us: %.2f" % (dur / 1e3),
+             "effective_clock_GHz: %.3f" % (avg("GRBM_GUI_ACTIVE") / N_XCD /
+                                            dur),
+             "valu_instr_rate_T_lane_ops: %.2f" % (
+                 avg("SQ_INSTS_VALU") * 64 / dur / 1e3),
+             "valu_peak_at_effective_clock_T: %.2f" % (
+                 256 * 64 * avg("GRBM_GUI_ACTIVE") / N_XCD / dur / 1e3)]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main(argv):
+    if len(argv) >= 5 and argv[1] == "valu":
+        valu(argv[2], argv[3], " ".join(argv[4:]))
+        return 0
     if len(argv) >= 5 and argv[1] == "trace":
         trace(argv[2], argv[3], " ".join(argv[4:]))
     elif len(argv) >= 7 and argv[1] == "traffic":
