@@ -18,7 +18,9 @@ kernels run on.  ``cpu_baseline`` times the CPU oracle on the host cores.
 ``batched`` adds the fused batched workload (512 requests from 32 clients,
 one launch) against 512 plain launches; ``serving`` adds the Poisson serving
 workload (continuous batching vs a plain launch per request, p50/p99) and a
-rate sweep for the equal-p99 comparison.  Only one GPU is used.
+rate sweep for the equal-p99 comparison; ``host_resident`` ciphers the same
+1 GiB from pinned host memory to pinned host memory through each transfer
+mode, beside the host link's measured rates.  Only one GPU is used.
 """
 from __future__ import annotations
 
@@ -262,6 +264,114 @@ def calibrate(ms, torch):
             "note": "best of 5; copy counts read + write bytes"}
 
 
+PCIE_GEN5_X16_GBPS = 32e9 * 16 / 8 * 128 / 130 / 1e9   # 63.0 per direction
+
+
+def run_host(args, ms, torch, b):
+    """Host-resident pages: 1 GiB in pinned host memory ciphered host ->
+    host through each transfer mode, beside the link's own rates (copy
+    engines and the copy kernel, each direction alone and both at once)."""
+    import numpy as np
+    import oracle
+    eng = ms.Engine(0)
+    n = b.data.shape[0]
+    nbytes = n * 4096
+    src = eng.host_alloc(nbytes)
+    dst = eng.host_alloc(nbytes)
+    src.array[:] = b.data.reshape(-1)
+    dev_a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dev_b = torch.empty_like(dev_a)
+    s1 = torch.cuda.Stream()
+    s2 = torch.cuda.Stream()
+
+    def timed(fn, reps=3):
+        best = None
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s1)
+            s2.wait_event(e0)
+            fn()
+            e2 = torch.cuda.Event()
+            e2.record(s2)
+            s1.wait_event(e2)
+            e1.record(s1)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 1e3
+            if r:
+                best = t if best is None else min(best, t)
+        return best
+
+    def probe(src_p, dst_p, engine, stream):
+        st = ms.ms_probe_link(eng.ctx, src_p, dst_p, nbytes, engine,
+                              stream.cuda_stream)
+        if st:
+            raise RuntimeError("ms_probe_link: " + ms.ms_status_str(st))
+
+    link = {}
+    for name, engine in (("dma", 1), ("kernel", 0)):
+        t = timed(lambda: probe(src.ptr, dev_a.data_ptr(), engine, s1))
+        link[name + "_h2d_GBps"] = round(nbytes / t / 1e9, 2)
+        t = timed(lambda: probe(dev_b.data_ptr(), dst.ptr, engine, s1))
+        link[name + "_d2h_GBps"] = round(nbytes / t / 1e9, 2)
+        t = timed(lambda: (probe(src.ptr, dev_a.data_ptr(), engine, s1),
+                           probe(dev_b.data_ptr(), dst.ptr, engine, s2)))
+        link[name + "_both_ways_GBps_each"] = round(nbytes / t / 1e9, 2)
+    key = eng.key_load(b.key)
+    nonce = ms.linear_nonce(b.nonce_base, b.nonce_stride, b.nonce_tag)
+    sample = [0, 1, n // 2, n - 1]
+    want = oracle.cipher_pages(
+        b.key, np.stack([np.frombuffer(oracle.nonce_linear(
+            i, b.nonce_base, b.nonce_stride, b.nonce_tag), np.uint8)
+            for i in sample]), b.data[sample])
+    modes = {}
+    for name, mode in (("mapped", ms.MS_HOST_MAPPED), ("dma", ms.MS_HOST_DMA),
+                       ("dma_in", ms.MS_HOST_DMA_IN),
+                       ("auto", ms.MS_HOST_AUTO)):
+        dst.array[:] = 0
+        t = timed(lambda: eng.encrypt_host_pages(key, src, dst, nonce,
+                                                 mode=mode, stream=s1))
+        ok = np.array_equal(dst.array.reshape(n, 4096)[sample], want)
+        if not ok:
+            raise RuntimeError("host mode %s differs from the oracle" % name)
+        modes[name] = {"GBps": round(nbytes / t / 1e9, 2),
+                       "ms": round(t * 1e3, 3)}
+    # one-page host -> host calls, issue to completion seen by the host (the
+    # service time of a single decrypt-on-fault)
+    one_page = {}
+    for name, mode in (("mapped", ms.MS_HOST_MAPPED), ("dma", ms.MS_HOST_DMA)):
+        lat = []
+        for r in range(220):
+            t0 = time.perf_counter()
+            eng.decrypt_host_pages(key, src, dst, nonce, n_pages=1, mode=mode,
+                                   stream=s1)
+            s1.synchronize()
+            lat.append(time.perf_counter() - t0)
+        lat = np.sort(np.array(lat[20:]) * 1e6)
+        one_page[name] = {"p50_us": round(float(np.percentile(lat, 50)), 1),
+                          "p99_us": round(float(np.percentile(lat, 99)), 1)}
+    best = max(modes, key=lambda k: modes[k]["GBps"])
+    both = max(link["kernel_both_ways_GBps_each"],
+               link["dma_both_ways_GBps_each"])
+    eng.key_destroy(key)
+    src.free()
+    dst.free()
+    eng.close()
+    del dev_a, dev_b
+    torch.cuda.empty_cache()
+    return {"pages": n,
+            "what": "host -> host encrypt of pinned host pages; GB/s = page "
+                    "bytes / time (each byte crosses the link twice); best "
+                    "of 3 after 1 warmup, HIP events",
+            "modes": modes, "best_mode": best, "link": link,
+            "one_page_latency": one_page,
+            "pcie_gen5_x16_GBps_per_direction": round(PCIE_GEN5_X16_GBPS, 1),
+            "frac_of_link_both_ways": round(modes[best]["GBps"] / both, 4),
+            "frac_of_pcie_spec": round(modes[best]["GBps"] /
+                                       PCIE_GEN5_X16_GBPS, 4)}
+
+
 def run_serving(args, ms, torch):
     """Poisson arrivals (20k req/s, 10 s, 1..256 pages log-uniform, 64 clients,
     admission cap 8 GiB) through continuous batching and through one plain
@@ -467,6 +577,7 @@ def main():
     ap.add_argument("--p99-bounds", type=float, nargs="*",
                     default=[50, 75, 100, 200, 500])
     ap.add_argument("--no-prefetch", action="store_true")
+    ap.add_argument("--no-host", action="store_true")
     ap.add_argument("--prefetch-window", type=int, default=8)
     ap.add_argument("--prefetch-train-steps", type=int, default=1500)
     ap.add_argument("--prefetch-min-prob", type=float, default=0.1)
@@ -534,6 +645,9 @@ def main():
     if not args.no_batched:
         log("batched workload")
         line["batched"] = run_batched(args, ms, torch)
+    if not args.no_host:
+        log("host-resident pages")
+        line["host_resident"] = run_host(args, ms, torch, b)
     if not args.no_serving:
         line["serving"] = run_serving(args, ms, torch)
     if not args.no_prefetch:

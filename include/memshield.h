@@ -119,7 +119,11 @@ typedef struct ms_config {
     uint32_t validate_pointers;   /* 1 (default): check every device range */
     uint32_t use_graphs;          /* 1 (default): ms_process_batch replays a
                                      captured hipGraph */
-    uint32_t reserved[4];
+    uint32_t host_chunk_pages;    /* staged host-page calls: pages per chunk
+                                     (default 16384, at most 65536) */
+    uint32_t host_stage_slots;    /* staged host-page calls: device staging
+                                     buffers of one chunk (default 3, 2..16) */
+    uint32_t reserved[2];
 } ms_config;
 
 /* Tunables of the fused batched launch, chosen by ms_autotune. */

@@ -40,6 +40,19 @@ ms_status ms_probe_copy(ms_ctx *ctx, const void *src, void *dst,
 ms_status ms_probe_valu(ms_ctx *ctx, uint32_t *out, uint32_t iters,
                         uint32_t grid_blocks, void *stream, uint64_t *ops_out);
 
+/*
+ * Host-link probe: move `bytes` (multiple of 16) from src to dst, where each
+ * side is device memory or pinned host memory (as for the calls of
+ * memshield_host.h), not overlapping.  engine 0: the copy kernel above, which
+ * reads and writes host memory through the link directly (the path of
+ * MS_HOST_MAPPED); engine 1: the copy engines (hipMemcpyAsync, the path of
+ * MS_HOST_DMA).  Host-to-device, device-to-host, and both at once on two
+ * streams give the link rates the host-page calls are compared against.
+ * Stream-ordered.  Errors: MS_EINVAL, MS_EDEVICE.
+ */
+ms_status ms_probe_link(ms_ctx *ctx, const void *src, void *dst,
+                        uint64_t bytes, int32_t engine, void *stream);
+
 /* Compute units of the context's device (the grid sizing unit above). */
 int ms_device_cu_count(ms_ctx *ctx);
 

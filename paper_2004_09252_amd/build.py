@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libmemshield.so")
 ARCH = "gfx950"
 
 SOURCES = ["page_cipher.hip", "engine.cpp", "probes.cpp", "tune_cache.cpp",
-           "serve_loadgen.cpp", "mlp_kernels.hip"]
+           "serve_loadgen.cpp", "mlp_kernels.hip", "host_pages.cpp"]
 
 # Packed FP32 instructions are switched off for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

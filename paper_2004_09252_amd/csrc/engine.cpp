@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "memshield.h"
+#include "ms_internal.h"
 #include "ms_kernels.h"
 #include "tune_cache.h"
 
@@ -150,6 +151,9 @@ struct ms_ctx {
   uint64_t inflight_bytes = 0;  // scheduler thread only (mirrored in stats)
 
   std::atomic<int32_t> sticky_error{0};
+
+  // ---- host-resident pages (host_pages.cpp) ----
+  HostPath* host = nullptr;
 
   // ---- stats ----
   std::atomic<uint64_t> st_submitted{0}, st_completed{0}, st_eagain{0},
@@ -720,6 +724,30 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
   return MS_OK;
 }
 
+// One run of pages with one key: the plain kernel, unroll 2, as many waves
+// as stay resident.
+ms_status launch_plain_run(ms_ctx* c, uint32_t slot, const void* src,
+                           void* dst, uint64_t n_pages, const ms_nonce& nonce,
+                           hipStream_t s) {
+  ms::PlainArgs a;
+  a.keys = c->d_keys;
+  a.src = static_cast<const uint8_t*>(src);
+  a.dst = static_cast<uint8_t*>(dst);
+  a.nonce_array = reinterpret_cast<const uint32_t*>(nonce.array);
+  a.nonce_base = nonce.base;
+  a.nonce_stride = nonce.stride;
+  a.first_page = 0;
+  a.n_pages = n_pages;
+  a.key_slot = slot;
+  a.nonce_tag = nonce.tag;
+  const uint32_t kind =
+      nonce.kind == MS_NONCE_ARRAY ? ms::kNonceArray : ms::kNonceLinear;
+  const Tuning t = plain_tuning(c);
+  return dev_err(c, ms::launch_plain(a, kind, (int)c->cfg.rounds,
+                                     (uint32_t)c->cu_count * t.waves_per_cu,
+                                     t.unroll, s));
+}
+
 ms_status plain_call(ms_ctx* c, ms_key key, const void* src, void* dst,
                      uint64_t n_pages, const ms_nonce* nonce, void* stream) {
   if (!c) return MS_EINVAL;
@@ -738,24 +766,8 @@ ms_status plain_call(ms_ctx* c, ms_key key, const void* src, void* dst,
   uint32_t slot = 0;
   st = check_request(c, r, &slot, false);
   if (st) return st;
-  ms::PlainArgs a;
-  a.keys = c->d_keys;
-  a.src = static_cast<const uint8_t*>(src);
-  a.dst = static_cast<uint8_t*>(dst);
-  a.nonce_array = reinterpret_cast<const uint32_t*>(nonce->array);
-  a.nonce_base = nonce->base;
-  a.nonce_stride = nonce->stride;
-  a.first_page = 0;
-  a.n_pages = n_pages;
-  a.key_slot = slot;
-  a.nonce_tag = nonce->tag;
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
-  const uint32_t kind =
-      nonce->kind == MS_NONCE_ARRAY ? ms::kNonceArray : ms::kNonceLinear;
-  const Tuning t = plain_tuning(c);
-  return dev_err(c, ms::launch_plain(a, kind, (int)c->cfg.rounds,
-                                     (uint32_t)c->cu_count * t.waves_per_cu,
-                                     t.unroll, s));
+  return launch_plain_run(c, slot, src, dst, n_pages, *nonce, s);
 }
 
 ms_status install_key(ms_ctx* c, ms_key* out) {
@@ -800,6 +812,8 @@ void ms_config_default(ms_config* cfg) {
   cfg->prefetch_depth = 4096;
   cfg->validate_pointers = 1;
   cfg->use_graphs = 1;
+  cfg->host_chunk_pages = 16384;
+  cfg->host_stage_slots = 3;
 }
 
 const char* ms_status_str(ms_status st) {
@@ -834,6 +848,11 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
   if (cfg.inflight_batches == 0 || cfg.inflight_batches > 64)
     return MS_EINVAL;
   if (cfg.admission_cap_bytes < MS_PAGE_SIZE) return MS_EINVAL;
+  if (cfg.host_chunk_pages == 0) cfg.host_chunk_pages = 16384;
+  if (cfg.host_stage_slots == 0) cfg.host_stage_slots = 3;
+  if (cfg.host_chunk_pages > 65536 || cfg.host_stage_slots < 2 ||
+      cfg.host_stage_slots > 16)
+    return MS_EINVAL;
   int ndev = 0;
   if (!hip_ok(hipGetDeviceCount(&ndev))) return MS_EDEVICE;
   if (hip_device < 0 || hip_device >= ndev) return MS_EINVAL;
@@ -865,6 +884,7 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
   if (!st && !hip_ok(hipHostMalloc(reinterpret_cast<void**>(&c->h_staging),
                                    MS_KEY_BYTES, hipHostMallocDefault)))
     st = MS_ENOMEM;
+  if (!st && !(c->host = ms_internal_host_path_create())) st = MS_ENOMEM;
   if (!st) {
     secure_zero(c->h_staging, MS_KEY_BYTES);
     c->key_gen.assign(cfg.max_keys, 0);
@@ -919,6 +939,8 @@ ms_status ms_shutdown(ms_ctx* c) {
   c->q_cv.notify_all();
   if (c->scheduler.joinable()) c->scheduler.join();
   (void)hipDeviceSynchronize();
+  if (c->host) ms_internal_host_path_destroy(c->host);
+  c->host = nullptr;
   if (c->d_keys) {
     (void)hipMemset(c->d_keys, 0, (size_t)c->cfg.max_keys * MS_KEY_BYTES);
     (void)hipDeviceSynchronize();
@@ -1284,7 +1306,7 @@ int ms_debug_staging_is_zero(ms_ctx* c) {
 
 }  // extern "C"
 
-// ------------------------------------------- internal hooks for probes ---
+// ------------------------- internal hooks for the other host sources ---
 
 int ms_internal_device(ms_ctx* c) { return c->device; }
 int ms_internal_cu_count(ms_ctx* c) { return c->cu_count; }
@@ -1296,3 +1318,15 @@ ms_status ms_internal_check_range(ms_ctx* c, const void* p, uint64_t bytes,
   return check_device_range(c, p, bytes, align);
 }
 ms_status ms_internal_dev_err(ms_ctx* c, hipError_t e) { return dev_err(c, e); }
+const ms_config& ms_internal_config(ms_ctx* c) { return c->cfg; }
+ms_status ms_internal_sticky(ms_ctx* c) { return check_sticky(c); }
+bool ms_internal_resolve_key(ms_ctx* c, ms_key key, uint32_t* slot) {
+  return resolve_key(c, key, slot);
+}
+ms_status ms_internal_launch_plain(ms_ctx* c, uint32_t key_slot,
+                                   const void* src, void* dst,
+                                   uint64_t n_pages, const ms_nonce& nonce,
+                                   hipStream_t stream) {
+  return launch_plain_run(c, key_slot, src, dst, n_pages, nonce, stream);
+}
+HostPath* ms_internal_host_path(ms_ctx* c) { return c->host; }

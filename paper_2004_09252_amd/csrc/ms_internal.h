@@ -1,0 +1,38 @@
+// Hooks into the engine context (engine.cpp) for the library's other host
+// sources.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "memshield.h"
+
+struct HostPath;  // host-resident page state, defined in host_pages.cpp
+
+int ms_internal_device(ms_ctx* c);
+int ms_internal_cu_count(ms_ctx* c);
+const ms_config& ms_internal_config(ms_ctx* c);
+// The caller's stream, or the context's stream for NULL.
+hipStream_t ms_internal_stream(ms_ctx* c, void* stream);
+// A device range [p, p+bytes) inside one allocation of the context's device.
+ms_status ms_internal_check_range(ms_ctx* c, const void* p, uint64_t bytes,
+                                  uint64_t align);
+// Maps a HIP error to MS_EDEVICE and makes it sticky.
+ms_status ms_internal_dev_err(ms_ctx* c, hipError_t e);
+// MS_EDEVICE once a device error has been seen, MS_OK otherwise.
+ms_status ms_internal_sticky(ms_ctx* c);
+// Key handle -> key-table row; false for an unknown or stale handle.
+bool ms_internal_resolve_key(ms_ctx* c, ms_key key, uint32_t* slot);
+// One plain launch (split where a launch would exceed its page limit) of
+// n_pages pages from src to dst, both GPU-visible addresses, page p taking
+// the nonce of page p of `nonce`.  No argument checks.
+ms_status ms_internal_launch_plain(ms_ctx* c, uint32_t key_slot,
+                                   const void* src, void* dst,
+                                   uint64_t n_pages, const ms_nonce& nonce,
+                                   hipStream_t stream);
+
+// Owned by host_pages.cpp: created by ms_init, destroyed by ms_shutdown
+// after the device is idle.
+HostPath* ms_internal_host_path_create();
+void ms_internal_host_path_destroy(HostPath* h);
+HostPath* ms_internal_host_path(ms_ctx* c);

@@ -2,15 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include "memshield_probe.h"
+#include "ms_internal.h"
 #include "ms_kernels.h"
-
-// Defined in engine.cpp: the pieces of the context the probes need.
-int ms_internal_device(ms_ctx* c);
-int ms_internal_cu_count(ms_ctx* c);
-hipStream_t ms_internal_stream(ms_ctx* c, void* stream);
-ms_status ms_internal_check_range(ms_ctx* c, const void* p, uint64_t bytes,
-                                  uint64_t align);
-ms_status ms_internal_dev_err(ms_ctx* c, hipError_t e);
 
 extern "C" {
 

@@ -17,6 +17,8 @@ import ctypes
 import os
 import threading
 
+import numpy as np
+
 import torch  # loaded first so that the library binds to torch's HIP runtime
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -42,6 +44,11 @@ MS_ENCRYPT = 0
 MS_DECRYPT = 1
 MS_NONCE_ARRAY = 0
 MS_NONCE_LINEAR = 1
+# ms_host_mode (include/memshield_host.h)
+MS_HOST_AUTO = 0
+MS_HOST_MAPPED = 1
+MS_HOST_DMA = 2
+MS_HOST_DMA_IN = 3
 
 
 class ms_nonce(ctypes.Structure):
@@ -67,7 +74,9 @@ class ms_config(ctypes.Structure):
                 ("prefetch_depth", ctypes.c_uint32),
                 ("validate_pointers", ctypes.c_uint32),
                 ("use_graphs", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 4)]
+                ("host_chunk_pages", ctypes.c_uint32),
+                ("host_stage_slots", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class ms_tuning(ctypes.Structure):
@@ -150,6 +159,13 @@ _SIGS = {
     "ms_probe_copy": ([_P, _P, _P, _U64, _U32, _P], _I32),
     "ms_probe_valu": ([_P, _P, _U32, _U32, _P, ctypes.POINTER(_U64)], _I32),
     "ms_device_cu_count": ([_P], ctypes.c_int),
+    "ms_probe_link": ([_P, _P, _P, _U64, _I32, _P], _I32),
+    "ms_host_alloc": ([_P, _U64, ctypes.POINTER(_P)], _I32),
+    "ms_host_free": ([_P, _P], _I32),
+    "ms_encrypt_host_pages": ([_P, _U64, _P, _P, _U64,
+                               ctypes.POINTER(ms_nonce), _I32, _P], _I32),
+    "ms_decrypt_host_pages": ([_P, _U64, _P, _P, _U64,
+                               ctypes.POINTER(ms_nonce), _I32, _P], _I32),
     "ms_mlp_offsets": ([ctypes.POINTER(ms_mlp_shape), ctypes.POINTER(_U64)],
                        _U64),
     "ms_mlp_workspace_bytes": ([ctypes.POINTER(ms_mlp_shape), _I32], _U64),
@@ -333,6 +349,32 @@ def ms_device_cu_count(ctx) -> int:
     return _L().ms_device_cu_count(ctx)
 
 
+def ms_probe_link(ctx, src, dst, nbytes, engine, stream=None) -> int:
+    return _L().ms_probe_link(ctx, src, dst, nbytes, engine, stream)
+
+
+def ms_host_alloc(ctx, nbytes: int):
+    p = ctypes.c_void_p()
+    st = _L().ms_host_alloc(ctx, nbytes, ctypes.byref(p))
+    return st, p.value
+
+
+def ms_host_free(ctx, ptr) -> int:
+    return _L().ms_host_free(ctx, ptr)
+
+
+def ms_encrypt_host_pages(ctx, key, src, dst, n_pages, nonce: ms_nonce,
+                          mode=MS_HOST_AUTO, stream=None) -> int:
+    return _L().ms_encrypt_host_pages(ctx, key, src, dst, n_pages,
+                                      ctypes.byref(nonce), mode, stream)
+
+
+def ms_decrypt_host_pages(ctx, key, src, dst, n_pages, nonce: ms_nonce,
+                          mode=MS_HOST_AUTO, stream=None) -> int:
+    return _L().ms_decrypt_host_pages(ctx, key, src, dst, n_pages,
+                                      ctypes.byref(nonce), mode, stream)
+
+
 def ms_serve_run(ctx, trace: ms_serve_trace, keys, src_pool, src_pages,
                  dst_pool, dst_pages, mode, submit_threads, latency_out=None):
     """latency_out: optional float64 numpy array of trace.n entries."""
@@ -422,6 +464,35 @@ def request(key: int, src: torch.Tensor, dst: torch.Tensor, n_pages: int,
                       n_pages, nonce, 0, 0)
 
 
+class HostBuffer:
+    """Pinned, GPU-mapped host memory from ms_host_alloc; ``array`` is a
+    numpy uint8 view of it.  Freed (after being zeroed) by ``free`` or when
+    the owning engine closes."""
+
+    def __init__(self, engine, ptr: int, nbytes: int):
+        self.engine, self.ptr, self.nbytes = engine, ptr, nbytes
+        self.array = np.ctypeslib.as_array(
+            (ctypes.c_uint8 * nbytes).from_address(ptr))
+
+    def data_ptr(self) -> int:
+        return self.ptr
+
+    def free(self):
+        if self.ptr and self.engine.ctx:
+            self.array = None
+            _check(ms_host_free(self.engine.ctx, self.ptr), "ms_host_free")
+        self.ptr = 0
+
+
+def _addr(buf) -> int:
+    return buf.data_ptr()
+
+
+def _nbytes(buf) -> int:
+    return buf.nbytes if isinstance(buf, HostBuffer) else \
+        buf.numel() * buf.element_size()
+
+
 class Engine:
     """One engine context on a GPU; buffers are torch uint8 tensors."""
 
@@ -478,6 +549,29 @@ class Engine:
     def decrypt_pages(self, key, src, dst, nonce, n_pages=None, stream=None):
         self._pages(ms_decrypt_pages, "ms_decrypt_pages", key, src, dst, nonce,
                     n_pages, stream)
+
+    def host_alloc(self, nbytes: int) -> HostBuffer:
+        st, p = ms_host_alloc(self.ctx, nbytes)
+        _check(st, "ms_host_alloc")
+        return HostBuffer(self, p, nbytes)
+
+    def _host_pages(self, fn, name, key, src, dst, nonce, n_pages, mode,
+                    stream):
+        if n_pages is None:
+            n_pages = _nbytes(src) // PAGE_SIZE
+        _check(fn(self.ctx, key, _addr(src), _addr(dst), n_pages, nonce, mode,
+                  _stream_handle(stream)), name)
+
+    def encrypt_host_pages(self, key, src, dst, nonce, n_pages=None,
+                           mode=MS_HOST_AUTO, stream=None):
+        """src/dst: HostBuffer, pinned CPU tensor or CUDA tensor."""
+        self._host_pages(ms_encrypt_host_pages, "ms_encrypt_host_pages", key,
+                         src, dst, nonce, n_pages, mode, stream)
+
+    def decrypt_host_pages(self, key, src, dst, nonce, n_pages=None,
+                           mode=MS_HOST_AUTO, stream=None):
+        self._host_pages(ms_decrypt_host_pages, "ms_decrypt_host_pages", key,
+                         src, dst, nonce, n_pages, mode, stream)
 
     def process_batch(self, reqs, stream=None):
         _check(ms_process_batch(self.ctx, reqs, _stream_handle(stream)),

@@ -67,14 +67,38 @@ def test_bad_config_rejected_before_device_use(lib):
     cfg.queue_depth = 1000   # not a power of two
     st, _ = ms.ms_init(0, cfg)
     assert st == ms.MS_EINVAL
+    for field, value in (("host_stage_slots", 1), ("host_stage_slots", 17),
+                         ("host_chunk_pages", 65537)):
+        cfg = ms.ms_config_default()
+        setattr(cfg, field, value)
+        st, _ = ms.ms_init(0, cfg)
+        assert st == ms.MS_EINVAL, field
+
+
+def test_host_path_defaults_and_null_context(lib):
+    from paper_2004_09252_amd import memshield as ms
+    cfg = ms.ms_config_default()
+    assert cfg.host_chunk_pages == 16384 and cfg.host_stage_slots == 3
+    n = ms.linear_nonce(0, 1, 0)
+    assert ms.ms_encrypt_host_pages(None, 1, None, None, 1, n, 0) == \
+        ms.MS_EINVAL
+    assert ms.ms_host_alloc(None, 4096)[0] == ms.MS_EINVAL
+    assert ms.ms_host_free(None, None) == ms.MS_EINVAL
+    assert ms.ms_probe_link(None, None, None, 16, 0) == ms.MS_EINVAL
 
 
 def test_headers_compile_as_c(tmp_path):
     c = tmp_path / "t.c"
     incs = "".join('#include "%s"\n' % h for h in sorted(os.listdir(INCLUDE))
                    if h.endswith(".h"))
-    c.write_text(incs + 'int main(void){ ms_config c; ms_config_default(&c);'
-                 ' return (int)sizeof(ms_request) == 80 ? 0 : 1; }\n')
+    # layout checks at compile time (a negative array size fails the build)
+    c.write_text(incs +
+                 'typedef char req_is_80[sizeof(ms_request) == 80 ? 1 : -1];\n'
+                 'typedef char cfg_is_56[sizeof(ms_config) == 56 ? 1 : -1];\n'
+                 'typedef char nonce_is_32[sizeof(ms_nonce) == 32 ? 1 : -1];\n'
+                 'int main(void){ ms_config c; req_is_80 a; cfg_is_56 b;'
+                 ' nonce_is_32 d; (void)a; (void)b; (void)d;'
+                 ' ms_config_default(&c); return 0; }\n')
     subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror",
                            "-I", INCLUDE, "-c", str(c), "-o",
                            str(tmp_path / "t.o")])
@@ -86,6 +110,7 @@ def test_struct_layouts_match_binding():
     assert ctypes.sizeof(ms.ms_nonce) == 32
     assert ctypes.sizeof(ms.ms_request) == 80
     assert ctypes.sizeof(ms.ms_tuning) == 24
+    assert ctypes.sizeof(ms.ms_config) == 56
 
 
 def test_cipher_kernels_use_no_scratch(tmp_path):
