@@ -578,6 +578,9 @@ def main():
                     default=[50, 75, 100, 200, 500])
     ap.add_argument("--no-prefetch", action="store_true")
     ap.add_argument("--no-host", action="store_true")
+    ap.add_argument("--host-only", action="store_true",
+                    help="run only the host-resident section and print its "
+                         "JSON (for profiling that path alone)")
     ap.add_argument("--prefetch-window", type=int, default=8)
     ap.add_argument("--prefetch-train-steps", type=int, default=1500)
     ap.add_argument("--prefetch-min-prob", type=float, default=0.1)
@@ -598,6 +601,10 @@ def main():
 
     log("generating bulk workload (%d pages)" % args.pages)
     b = workloads.bulk(seed=2, n_pages=args.pages)
+    if args.host_only:
+        print(json.dumps({"host_resident": run_host(args, ms, torch, b)}),
+              flush=True)
+        return
     log("timing %d steps after %d warmup" % (args.steps, args.warmup))
     dt, launch_ms = run_bulk(args, ms, torch, b)
     n = args.pages

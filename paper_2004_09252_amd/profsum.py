@@ -6,6 +6,7 @@ Usage (from the repository root, on the databases a profiling run left):
     python -m paper_2004_09252_amd.profsum traffic <fetch.db> <write.db> \
         <out.txt> <cmd-fetch> <cmd-write>
     python -m paper_2004_09252_amd.profsum valu <valu.db> <out.txt> <cmd>
+    python -m paper_2004_09252_amd.profsum host <csv-dir> <out.md> <cmd>
 
 ``trace`` writes the kernel-trace statistics (rocprofv3 --kernel-trace
 --stats): per kernel and grid size, the number of dispatches and their
@@ -172,7 +173,47 @@ def valu(db_path: str, out_path: str, cmd: str) -> None:
         f.write("\n".join(lines) + "\n")
 
 
+def host(trace_dir: str, out_path: str, cmd: str) -> None:
+    """Kernel dispatches and memory copies of a host-resident run, from the
+    CSV traces of rocprofv3 --kernel-trace --memory-copy-trace
+    --output-format csv: per kernel (and grid) or copy direction, the count
+    and the average, minimum and maximum duration."""
+    import csv
+    import glob
+    groups = collections.defaultdict(list)
+    for f in glob.glob(os.path.join(trace_dir, "**", "*_kernel_trace.csv"),
+                       recursive=True):
+        for r in csv.DictReader(open(f)):
+            blocks = int(r["Grid_Size_X"]) // max(int(r["Workgroup_Size_X"]), 1)
+            groups[("kernel", _short(r["Kernel_Name"]), blocks)].append(
+                int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    for f in glob.glob(os.path.join(trace_dir, "**",
+                                    "*_memory_copy_trace.csv"),
+                       recursive=True):
+        for r in csv.DictReader(open(f)):
+            groups[("copy", r["Direction"].replace("MEMORY_COPY_", ""), 0)
+                   ].append(int(r["End_Timestamp"]) -
+                            int(r["Start_Timestamp"]))
+    lines = ["# rocprofv3 kernel and memory-copy trace: host-resident pages",
+             "", "Command (from the repository root, after `cd /tmp && "
+             "export TMPDIR=/tmp`):", "", "    " + cmd, "",
+             "Durations in microseconds; `blocks` is the grid size in "
+             "256-thread workgroups (0 for copy-engine transfers).", "",
+             "| kind | name | blocks | calls | avg us | min us | max us | "
+             "total ms |", "|---|---|---|---|---|---|---|---|"]
+    rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
+    for (kind, name, blocks), d in rows[:30]:
+        lines.append("| %s | %s | %d | %d | %.2f | %.2f | %.2f | %.2f |" % (
+            kind, name, blocks, len(d), sum(d) / len(d) / 1e3,
+            min(d) / 1e3, max(d) / 1e3, sum(d) / 1e6))
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main(argv):
+    if len(argv) >= 5 and argv[1] == "host":
+        host(argv[2], argv[3], " ".join(argv[4:]))
+        return 0
     if len(argv) >= 5 and argv[1] == "valu":
         valu(argv[2], argv[3], " ".join(argv[4:]))
         return 0
