@@ -48,8 +48,10 @@ METRIC = ("page encrypt+decrypt GB/s on 1 MI355X (batched vs plain); "
           "p50/p99 request latency")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles",
                             "traffic_plain_pages_kernel_bulk_1gib.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2004_09252_amd", "csrc",
-                             "page_cipher.hip")
+# the sources that define the bulk kernel (its digest ties the stored
+# traffic counters to this kernel)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2004_09252_amd", "csrc", f)
+                  for f in ("page_cipher.hip", "cipher_core.h")]
 
 
 def log(msg):
@@ -57,7 +59,10 @@ def log(msg):
 
 
 def kernel_source_digest() -> str:
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def read_traffic():

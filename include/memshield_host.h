@@ -52,8 +52,9 @@ typedef enum ms_host_mode {
 } ms_host_mode;
 
 /*
- * Allocate `bytes` (> 0) of pinned, GPU-mapped host memory, zero-filled, for
- * use as page buffers of the calls below.  *out receives the address (valid
+ * Allocate `bytes` (> 0) of pinned, GPU-mapped, coherent (fine-grained) host
+ * memory, zero-filled, for use as page buffers of the calls below and of
+ * the resident-key engine.  *out receives the address (valid
  * on the host and, through the same address, on the GPU).  Errors:
  * MS_EINVAL, MS_ENOMEM.
  */

@@ -935,6 +935,7 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
 ms_status ms_shutdown(ms_ctx* c) {
   if (!c) return MS_OK;
   (void)hipSetDevice(c->device);
+  ms_internal_resident_stop_all(c);
   c->stop.store(true);
   c->q_cv.notify_all();
   if (c->scheduler.joinable()) c->scheduler.join();

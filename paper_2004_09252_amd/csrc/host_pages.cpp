@@ -282,6 +282,16 @@ ms_status host_call(ms_ctx* c, ms_key key, const void* src, void* dst,
 
 }  // namespace
 
+ms_status ms_internal_classify_host(ms_ctx* c, const void* p, uint64_t bytes,
+                                    uint64_t align, uint64_t* gpu) {
+  Buf b{};
+  ms_status st = classify(c, p, bytes, align, &b);
+  if (st) return st;
+  if (b.where != Where::kHost) return MS_EINVAL;
+  *gpu = reinterpret_cast<uint64_t>(b.gpu);
+  return MS_OK;
+}
+
 HostPath* ms_internal_host_path_create() {
   return new (std::nothrow) HostPath();
 }
@@ -302,7 +312,9 @@ ms_status ms_host_alloc(ms_ctx* c, uint64_t bytes, void** out) {
   if (!c || !out || bytes == 0) return MS_EINVAL;
   HostPath* h = ms_internal_host_path(c);
   void* p = nullptr;
-  if (!hip_ok(hipHostMalloc(&p, bytes, hipHostMallocDefault)) || !p) {
+  // coherent (fine-grained): a running kernel may read what the host writes
+  // and the other way round, without a dispatch boundary in between
+  if (!hip_ok(hipHostMalloc(&p, bytes, hipHostMallocCoherent)) || !p) {
     (void)hipGetLastError();
     return MS_ENOMEM;
   }

@@ -36,3 +36,12 @@ ms_status ms_internal_launch_plain(ms_ctx* c, uint32_t key_slot,
 HostPath* ms_internal_host_path_create();
 void ms_internal_host_path_destroy(HostPath* h);
 HostPath* ms_internal_host_path(ms_ctx* c);
+
+// [p, p+bytes) in pinned host memory mapped into the GPU's address space
+// (checked against its allocation when pointer validation is on); *gpu gets
+// the address the GPU uses for p.  MS_EINVAL for anything else.
+ms_status ms_internal_classify_host(ms_ctx* c, const void* p, uint64_t bytes,
+                                    uint64_t align, uint64_t* gpu);
+
+// Stops every resident-key engine of the context (resident.cpp).
+void ms_internal_resident_stop_all(ms_ctx* c);

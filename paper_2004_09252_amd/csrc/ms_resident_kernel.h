@@ -1,0 +1,70 @@
+// Memory shared between the resident-key kernel (resident.hip) and its host
+// side (resident.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ms {
+
+// One descriptor of the host's submission ring: a run of pages (at most
+// max_pages) in GPU-visible host memory, ciphered with the resident key and
+// the linear nonce rule.  64 bytes, in pinned host memory.
+struct RkDesc {
+  uint64_t src;           // GPU-visible address of the first source page
+  uint64_t dst;           // same for the destination
+  uint64_t nonce_base;    // nonce of page 0 (state words 13..14)
+  uint64_t nonce_stride;  // nonce increment per page
+  uint64_t seq;           // ring position the descriptor was written for
+  uint32_t n_pages;
+  uint32_t tag;           // state word 15
+  uint64_t pad[2];
+};
+static_assert(sizeof(RkDesc) == 64, "RkDesc layout");
+
+// Control words in pinned host memory.  The host writes `published`,
+// `heartbeat` and `stop`; the kernel writes `ready`, `exited` and `error`.
+struct RkHostCtl {
+  uint64_t published;   // ring positions [0, published) hold descriptors
+  uint64_t heartbeat;   // bumped by host calls: counts as activity
+  uint32_t stop;        // 1: the kernel ends
+  uint32_t ready;       // 1: every worker holds the key, its copy is wiped
+  uint32_t exited;      // 1: the poller has left; workers follow
+  uint32_t error;       // nonzero: a descriptor failed the kernel's checks
+  uint64_t pad[4];
+};
+static_assert(sizeof(RkHostCtl) == 64, "RkHostCtl layout");
+
+// Control words in device memory, zeroed before the launch.
+struct RkDevCtl {
+  uint64_t claimed;    // next ring position a worker takes
+  uint64_t published;  // the poller's copy of RkHostCtl::published
+  uint32_t stop;       // poller -> workers
+  uint32_t key_loads;  // workers holding the key
+  uint64_t pad[5];
+};
+static_assert(sizeof(RkDevCtl) == 64, "RkDevCtl layout");
+
+struct RkArgs {
+  const RkDesc* ring;     // host, ring_mask + 1 descriptors
+  uint64_t* completed;    // host, per slot: position + 1 of the last
+                          // descriptor finished in it
+  RkHostCtl* hctl;
+  RkDevCtl* dctl;
+  uint32_t* key_buf;      // device, 8 words; wiped once every worker has them
+  uint64_t idle_ticks;    // 100 MHz ticks without host activity before the
+                          // kernel ends itself; 0 = no limit
+  uint32_t ring_mask;
+  uint32_t n_workers;     // worker waves (the poller is one more wave)
+  uint32_t max_pages;     // pages per descriptor
+  uint32_t pad;
+};
+
+// Kernel entry points (plain C names in the separately built code object),
+// one per round count; launched as (n_workers + 1) waves in 256-thread
+// workgroups with 16 KiB of LDS per workgroup.
+constexpr const char* kResidentKernel20 = "ms_resident_pages_r20.kd";
+constexpr const char* kResidentKernel12 = "ms_resident_pages_r12.kd";
+constexpr const char* kResidentKernel8 = "ms_resident_pages_r8.kd";
+
+}  // namespace ms

@@ -1,0 +1,229 @@
+// Resident-key page cipher for gfx950: MemShield's own GPU design (section
+// 4.4) on CDNA4.
+//
+// The paper keeps its 256-bit key only in the registers of a GPU kernel that
+// never ends, and feeds that kernel pages through a multiple-producer ring
+// in memory mapped between host and device; host threads enqueue pages, GPU
+// workers take them.  Here:
+//   * one dispatch, on an HSA queue of its own (so no stream of the HIP
+//     runtime can wait behind it), holds `n_workers` worker waves plus one
+//     poller wave for as long as the host keeps it;
+//   * the key reaches the kernel once, through a 32-byte device buffer: each
+//     worker reads it with cache-bypassing vector loads into SGPRs (the
+//     compiler may not move it elsewhere: it is opaque after an empty asm),
+//     counts itself in, and the last worker zeroes the buffer and tells the
+//     host; from then on the key exists only in registers (no scratch: the
+//     kernel's resource usage is checked to be spill-free);
+//   * the host writes 64-byte descriptors (a run of host pages, its linear
+//     nonce) into a ring in pinned host memory and publishes a count; the
+//     poller wave reads that count over the link and mirrors it into device
+//     memory, so the idle workers, each holding a claimed ring position,
+//     wait on device memory instead of polling across the link;
+//   * a worker reads its descriptor and the pages with system-scope loads
+//     (coalesced 8-byte columns, no stale cached copy is possible), XORs the
+//     keystream, transposed through LDS as in the launch-per-call kernels,
+//     writes the pages back with system-scope stores, and after a release
+//     fence writes the position into the slot's completion word, which the
+//     host polls;
+//   * every wait is bounded: the poller leaves when the host sets `stop` or
+//     after `idle_ticks` without host activity, and the workers leave when
+//     the poller does, so the launch always drains;
+//   * control flow is wave-uniform everywhere (no lane-masked branches): a
+//     value one lane obtains (a claimed position) comes from an atomic all
+//     lanes execute, lane 0 adding 1 and the others 0, and control words are
+//     stored by all lanes with the same value.  A lane-0-only branch next to
+//     a loop back-edge can otherwise be compiled into an exec-mask loop that
+//     some lanes leave and others do not.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cipher_core.h"
+#include "ms_resident_kernel.h"
+
+namespace ms {
+namespace {
+
+__device__ __forceinline__ uint64_t ld_sys64(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t ld_sys32(const uint32_t* p) {
+  return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void st_sys64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void st_sys32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+// Page data: global address space (the addresses arrive as integers in the
+// descriptors), system scope.
+typedef __attribute__((address_space(1))) uint64_t gu64;
+__device__ __forceinline__ uint64_t ld_page(uint64_t addr) {
+  return __hip_atomic_load(reinterpret_cast<gu64*>(addr), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void st_page(uint64_t addr, uint64_t v) {
+  __hip_atomic_store(reinterpret_cast<gu64*>(addr), v, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint64_t ld_dev64(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_dev32(const uint32_t* p) {
+  return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The poller: mirror the host's published count into device memory; leave
+// on `stop` or after idle_ticks without a new descriptor or heartbeat.
+__device__ void poll_host(const RkArgs& a, uint32_t lane) {
+  uint64_t last_pub = 0, last_hb = 0;
+  uint64_t t_last = wall_clock64();
+  for (;;) {
+    if (uni(ld_sys32(&a.hctl->stop))) break;
+    const uint64_t pub = uni64(ld_sys64(&a.hctl->published));
+    const uint64_t hb = uni64(ld_sys64(&a.hctl->heartbeat));
+    const uint64_t now = wall_clock64();
+    if (pub != last_pub) {
+      __hip_atomic_store(&a.dctl->published, pub, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      last_pub = pub;
+      t_last = now;
+    } else if (hb != last_hb) {
+      last_hb = hb;
+      t_last = now;
+    } else if (a.idle_ticks != 0 && now - t_last > a.idle_ticks) {
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __hip_atomic_store(&a.dctl->stop, 1u, __ATOMIC_RELEASE,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&a.hctl->exited, 1u, __ATOMIC_RELEASE,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Cipher the pages of the descriptor at ring position `pos`, then mark the
+// position complete.  A descriptor that does not carry its own position, or
+// has a page count outside 1..max_pages, is not touched and raises `error`.
+template <int ROUNDS>
+__device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
+                          uint64_t pos, uint4* lds, uint32_t lane) {
+  const RkDesc* d = a.ring + (pos & a.ring_mask);
+  const uint64_t seq = uni64(ld_sys64(&d->seq));
+  const uint64_t src = uni64(ld_sys64(&d->src));
+  const uint64_t dst = uni64(ld_sys64(&d->dst));
+  const uint64_t nb = uni64(ld_sys64(&d->nonce_base));
+  const uint64_t ns = uni64(ld_sys64(&d->nonce_stride));
+  const uint64_t pt = uni64(ld_sys64(reinterpret_cast<const uint64_t*>(
+      &d->n_pages)));  // n_pages | tag << 32
+  const uint32_t n_pages = (uint32_t)pt;
+  const uint32_t tag = (uint32_t)(pt >> 32);
+  if (seq != pos || n_pages == 0 || n_pages > a.max_pages) {
+    st_sys32(&a.hctl->error, 1u);
+  } else {
+    for (uint32_t p = 0; p < n_pages; ++p) {
+      const uint64_t s = src + (uint64_t)p * kPageBytes;
+      const uint64_t o = dst + (uint64_t)p * kPageBytes;
+      // the page's 512 8-byte units: access q of lane l is unit 64*q + l,
+      // issued before the keystream so the link latency overlaps the rounds
+      uint64_t v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = ld_page(s + 8u * (q * 64 + lane));
+      const uint64_t nv = nb + (uint64_t)p * ns;
+      const uint32_t n[3] = {(uint32_t)nv, (uint32_t)(nv >> 32), tag};
+      uint32_t ks[16];
+      keystream<ROUNDS>(ks, k, n, lane);  // block `lane` = bytes 64*lane..
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        lds[lds_slot(lane * 4 + q)] =
+            make_uint4(ks[4 * q], ks[4 * q + 1], ks[4 * q + 2], ks[4 * q + 3]);
+      wave_lds_order();
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t unit = q * 64 + lane;  // bytes 8*unit .. 8*unit+7
+        const uint2 x = reinterpret_cast<const uint2*>(
+            &lds[lds_slot(unit >> 1)])[unit & 1];
+        st_page(o + 8u * unit, v[q] ^ (((uint64_t)x.y << 32) | x.x));
+      }
+      wave_lds_order();
+    }
+  }
+  // the page stores reach the host before the completion word does
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+  st_sys64(&a.completed[pos & a.ring_mask], pos + 1);
+}
+
+template <int ROUNDS>
+__device__ void serve_ring(const RkArgs& a, uint4* lds, uint32_t lane) {
+  uint32_t k[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) k[i] = uni(ld_sys32(a.key_buf + i));
+#pragma unroll
+  for (int i = 0; i < 8; ++i) asm volatile("" : "+s"(k[i]) : : "memory");
+  // one count per wave: lane 0 adds 1, the other lanes 0; lane 0's result
+  // is the count before this wave
+  const uint32_t before = uni(__hip_atomic_fetch_add(
+      &a.dctl->key_loads, lane == 0 ? 1u : 0u, __ATOMIC_ACQ_REL,
+      __HIP_MEMORY_SCOPE_AGENT));
+  if (before + 1 == a.n_workers) {
+    // every worker now holds the key in registers: wipe the memory copy
+    st_sys32(a.key_buf + (lane & 7u), 0u);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    st_sys32(&a.hctl->ready, 1u);
+  }
+  for (;;) {
+    if (uni(ld_dev32(&a.dctl->stop))) return;
+    const uint64_t pos = uni64(__hip_atomic_fetch_add(
+        &a.dctl->claimed, lane == 0 ? (uint64_t)1 : (uint64_t)0,
+        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    // wait on device memory until the position is published, or stop; the
+    // worker holding the next position to be published polls fastest
+    for (;;) {
+      const uint64_t pub = uni64(ld_dev64(&a.dctl->published));
+      if (pos < pub) break;
+      if (uni(ld_dev32(&a.dctl->stop))) return;
+      if (pos == pub)
+        __builtin_amdgcn_s_sleep(2);
+      else
+        __builtin_amdgcn_s_sleep(64);
+    }
+    serve_one<ROUNDS>(a, k, pos, lds, lane);
+  }
+}
+
+template <int ROUNDS>
+__device__ __forceinline__ void resident_pages(const RkArgs& a) {
+  __shared__ uint4 lds[kWavesPerBlock][256];
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t w = wave_in_block();
+  const uint32_t gw = blockIdx.x * kWavesPerBlock + w;
+  if (gw == 0) {
+    poll_host(a, lane);
+    return;
+  }
+  if (gw > a.n_workers) return;
+  serve_ring<ROUNDS>(a, lds[w], lane);
+}
+
+}  // namespace
+}  // namespace ms
+
+// Entry points by round count.  This file is built as its own code object
+// and dispatched by resident.cpp on a private HSA queue, so the names are
+// plain C symbols.
+extern "C" __global__ __launch_bounds__(ms::kBlockThreads) void
+ms_resident_pages_r20(ms::RkArgs a) {
+  ms::resident_pages<20>(a);
+}
+extern "C" __global__ __launch_bounds__(ms::kBlockThreads) void
+ms_resident_pages_r12(ms::RkArgs a) {
+  ms::resident_pages<12>(a);
+}
+extern "C" __global__ __launch_bounds__(ms::kBlockThreads) void
+ms_resident_pages_r8(ms::RkArgs a) {
+  ms::resident_pages<8>(a);
+}

@@ -13,9 +13,11 @@ Two layers:
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import threading
+import weakref
 
 import numpy as np
 
@@ -77,6 +79,13 @@ class ms_config(ctypes.Structure):
                 ("host_chunk_pages", ctypes.c_uint32),
                 ("host_stage_slots", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32 * 2)]
+
+
+class ms_resident_config(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_uint32), ("ring_depth", ctypes.c_uint32),
+                ("desc_pages", ctypes.c_uint32),
+                ("idle_limit_ms", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
 
 
 class ms_tuning(ctypes.Structure):
@@ -160,6 +169,17 @@ _SIGS = {
     "ms_probe_valu": ([_P, _P, _U32, _U32, _P, ctypes.POINTER(_U64)], _I32),
     "ms_device_cu_count": ([_P], ctypes.c_int),
     "ms_probe_link": ([_P, _P, _P, _U64, _I32, _P], _I32),
+    "ms_resident_config_default": ([ctypes.POINTER(ms_resident_config)],
+                                   None),
+    "ms_resident_start": ([_P, ctypes.POINTER(ms_resident_config),
+                           ctypes.c_char_p, ctypes.POINTER(_P)], _I32),
+    "ms_resident_submit": ([_P, _P, _P, _U64, ctypes.POINTER(ms_nonce),
+                            ctypes.POINTER(_U64)], _I32),
+    "ms_resident_poll": ([_P, ctypes.POINTER(_U64), ctypes.c_size_t,
+                          ctypes.POINTER(_I32), _U64], _I32),
+    "ms_resident_alive": ([_P], ctypes.c_int),
+    "ms_resident_stop": ([_P], _I32),
+    "ms_resident_debug_key_wiped": ([_P], ctypes.c_int),
     "ms_host_alloc": ([_P, _U64, ctypes.POINTER(_P)], _I32),
     "ms_host_free": ([_P, _P], _I32),
     "ms_encrypt_host_pages": ([_P, _U64, _P, _P, _U64,
@@ -353,6 +373,49 @@ def ms_probe_link(ctx, src, dst, nbytes, engine, stream=None) -> int:
     return _L().ms_probe_link(ctx, src, dst, nbytes, engine, stream)
 
 
+def ms_resident_config_default() -> ms_resident_config:
+    c = ms_resident_config()
+    _L().ms_resident_config_default(ctypes.byref(c))
+    return c
+
+
+def ms_resident_start(ctx, config: ms_resident_config | None = None,
+                      key: bytes | None = None):
+    r = ctypes.c_void_p()
+    st = _L().ms_resident_start(ctx, ctypes.byref(config)
+                                if config is not None else None,
+                                bytes(key) if key is not None else None,
+                                ctypes.byref(r))
+    return st, r.value
+
+
+def ms_resident_submit(r, src, dst, n_pages, nonce: ms_nonce):
+    t = ctypes.c_uint64()
+    st = _L().ms_resident_submit(r, src, dst, n_pages, ctypes.byref(nonce),
+                                 ctypes.byref(t))
+    return st, t.value
+
+
+def ms_resident_poll(r, tickets, timeout_ns: int = 0):
+    n = len(tickets)
+    t = (ctypes.c_uint64 * max(n, 1))(*tickets)
+    d = (ctypes.c_int32 * max(n, 1))()
+    st = _L().ms_resident_poll(r, t, n, d, timeout_ns)
+    return st, list(d)[:n]
+
+
+def ms_resident_alive(r) -> int:
+    return _L().ms_resident_alive(r)
+
+
+def ms_resident_stop(r) -> int:
+    return _L().ms_resident_stop(r)
+
+
+def ms_resident_debug_key_wiped(r) -> int:
+    return _L().ms_resident_debug_key_wiped(r)
+
+
 def ms_host_alloc(ctx, nbytes: int):
     p = ctypes.c_void_p()
     st = _L().ms_host_alloc(ctx, nbytes, ctypes.byref(p))
@@ -493,6 +556,61 @@ def _nbytes(buf) -> int:
         buf.numel() * buf.element_size()
 
 
+class Resident:
+    """A resident-key engine (include/memshield_resident.h) of an Engine.
+    Pages are HostBuffers (pinned, coherent host memory); nonces are
+    linear."""
+
+    def __init__(self, engine, handle: int):
+        self.engine, self.handle = engine, handle
+
+    def submit(self, src, dst, nonce, n_pages=None) -> int:
+        if n_pages is None:
+            n_pages = _nbytes(src) // PAGE_SIZE
+        st, t = ms_resident_submit(self.handle, _addr(src), _addr(dst),
+                                   n_pages, nonce)
+        _check(st, "ms_resident_submit")
+        return t
+
+    def poll(self, tickets, timeout_s: float = 0.0):
+        return ms_resident_poll(self.handle, tickets, int(timeout_s * 1e9))
+
+    def wait(self, tickets, timeout_s: float = 30.0):
+        st, done = self.poll(tickets, timeout_s)
+        _check(st, "ms_resident_poll")
+        if any(d != 1 for d in done):
+            raise MemShieldError(MS_ECANCELED, "ms_resident_poll")
+
+    def alive(self) -> bool:
+        return bool(self.handle) and ms_resident_alive(self.handle) == 1
+
+    def key_wiped(self) -> int:
+        return ms_resident_debug_key_wiped(self.handle)
+
+    def stop(self):
+        if self.handle:
+            st = MS_OK
+            if self.engine.ctx:
+                st = ms_resident_stop(self.handle)
+            self.handle = 0
+            if self in self.engine._residents:
+                self.engine._residents.remove(self)
+            _check(st, "ms_resident_stop")
+
+
+_live_engines = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_engines():
+    # a resident-key kernel must not outlive its process's last Python frame
+    for e in list(_live_engines):
+        try:
+            e.close()
+        except Exception:
+            pass
+
+
 class Engine:
     """One engine context on a GPU; buffers are torch uint8 tensors."""
 
@@ -503,11 +621,15 @@ class Engine:
                 raise TypeError("unknown config field %r" % k)
             setattr(cfg, k, v)
         self.device = device
+        self._residents = []
         st, self.ctx = ms_init(device, cfg)
         _check(st, "ms_init")
+        _live_engines.add(self)
 
     def close(self):
         if self.ctx:
+            for r in list(self._residents):
+                r.stop()
             ms_shutdown(self.ctx)
             self.ctx = None
 
@@ -549,6 +671,18 @@ class Engine:
     def decrypt_pages(self, key, src, dst, nonce, n_pages=None, stream=None):
         self._pages(ms_decrypt_pages, "ms_decrypt_pages", key, src, dst, nonce,
                     n_pages, stream)
+
+    def resident(self, key: bytes | None = None, **config) -> Resident:
+        cfg = ms_resident_config_default()
+        for k, v in config.items():
+            if not hasattr(cfg, k):
+                raise TypeError("unknown resident config field %r" % k)
+            setattr(cfg, k, v)
+        st, h = ms_resident_start(self.ctx, cfg, key)
+        _check(st, "ms_resident_start")
+        r = Resident(self, h)
+        self._residents.append(r)
+        return r
 
     def host_alloc(self, nbytes: int) -> HostBuffer:
         st, p = ms_host_alloc(self.ctx, nbytes)

@@ -17,8 +17,9 @@ per launch of the bulk plain page kernel.  Both counters are first calibrated
 on the copy probe, which reads and writes a known 1 GiB: the factor is
 (known bytes) / (counter bytes) for each counter, and the kernel's traffic is
 its counter bytes times that factor.  The summary records the SHA-256 of the
-kernel source so that a reader (bench.py) can tell when the kernel has
-changed since the counters were taken.
+kernel's sources (page_cipher.hip, cipher_core.h) so that a reader
+(bench.py) can tell when the kernel has changed since the counters were
+taken.
 """
 from __future__ import annotations
 
@@ -29,7 +30,8 @@ import sqlite3
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, "csrc", "page_cipher.hip")
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f)
+                  for f in ("page_cipher.hip", "cipher_core.h")]
 COPY_BYTES = 1 << 30
 BULK_KERNEL = "plain_pages_kernel<20, 2, 1u>"
 COPY_KERNEL = "copy_probe_kernel"
@@ -103,7 +105,10 @@ def traffic(fetch_db: str, write_db: str, out_path: str, cmd_f: str,
     fetch_b = kf * 1024.0 * ff
     write_b = kw * 1024.0 * fw
     algo = 2.0 * 262144 * 4096
-    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    digest = h.hexdigest()
     lines = [
         "# HBM traffic of the bulk plain page kernel (1 GiB pass, 262144 "
         "pages), from rocprofv3 counters",

@@ -113,9 +113,12 @@ def test_struct_layouts_match_binding():
     assert ctypes.sizeof(ms.ms_config) == 56
 
 
-def test_cipher_kernels_use_no_scratch(tmp_path):
+@pytest.mark.parametrize("source,min_kernels", [("page_cipher.hip", 8),
+                                                ("resident.hip", 3)])
+def test_cipher_kernels_use_no_scratch(tmp_path, source, min_kernels):
     """Compile the kernels with resource-usage remarks: every kernel must
-    report zero scratch bytes per lane (no register spill)."""
+    report zero scratch bytes per lane (no register spill), so the key and
+    the cipher state never reach per-lane memory (section 4.4)."""
     hipcc = "/opt/rocm/bin/hipcc"
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not present")
@@ -124,13 +127,13 @@ def test_cipher_kernels_use_no_scratch(tmp_path):
          "--cuda-device-only", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC,
          "-Rpass-analysis=kernel-resource-usage", "-c",
-         os.path.join(CSRC, "page_cipher.hip"), "-o", str(tmp_path / "k.o")],
+         os.path.join(CSRC, source), "-o", str(tmp_path / "k.o")],
         capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     names = re.findall(r"Function Name: (\S+)", r.stderr)
     scratch = [int(x) for x in
                re.findall(r"ScratchSize \[bytes/lane\]: (\d+)", r.stderr)]
-    assert len(names) >= 8 and len(names) == len(scratch)
+    assert len(names) >= min_kernels and len(names) == len(scratch)
     bad = [n for n, s in zip(names, scratch) if s != 0]
     assert not bad, bad
 
