@@ -123,7 +123,10 @@ typedef struct ms_config {
                                      (default 16384, at most 65536) */
     uint32_t host_stage_slots;    /* staged host-page calls: device staging
                                      buffers of one chunk (default 3, 2..16) */
-    uint32_t reserved[2];
+    uint32_t host_mapped_waves;   /* kernels that read or write host pages:
+                                     at most this many waves, so that few
+                                     reads wait on the link (default 128) */
+    uint32_t reserved[1];
 } ms_config;
 
 /* Tunables of the fused batched launch, chosen by ms_autotune. */

@@ -28,10 +28,9 @@
  *                   streams.
  *   MS_HOST_DMA_IN  copy engines inbound, the kernel writes the host
  *                   destination directly.
- * MS_HOST_AUTO selects MS_HOST_DMA for long runs (at least 8 chunks, with
- * chunks of at least 16384 pages), where the copy engines' two directions
- * outrun the kernel's own link traffic once the pipeline is full, and
- * MS_HOST_MAPPED otherwise (lowest latency: one launch, no staging).
+ * MS_HOST_AUTO selects MS_HOST_MAPPED: with its wave count capped
+ * (ms_config.host_mapped_waves) it matches or passes the staged pipeline at
+ * every run size on an MI355X host link, and has the lowest latency.
  * Whatever the mode, the output bytes are identical to those of
  * ms_encrypt_pages on the same key, nonce and input.
  */

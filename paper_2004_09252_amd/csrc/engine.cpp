@@ -728,7 +728,7 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
 // as stay resident.
 ms_status launch_plain_run(ms_ctx* c, uint32_t slot, const void* src,
                            void* dst, uint64_t n_pages, const ms_nonce& nonce,
-                           hipStream_t s) {
+                           hipStream_t s, uint32_t max_waves = 0) {
   ms::PlainArgs a;
   a.keys = c->d_keys;
   a.src = static_cast<const uint8_t*>(src);
@@ -743,8 +743,11 @@ ms_status launch_plain_run(ms_ctx* c, uint32_t slot, const void* src,
   const uint32_t kind =
       nonce.kind == MS_NONCE_ARRAY ? ms::kNonceArray : ms::kNonceLinear;
   const Tuning t = plain_tuning(c);
+  const uint32_t resident = (uint32_t)c->cu_count * t.waves_per_cu;
   return dev_err(c, ms::launch_plain(a, kind, (int)c->cfg.rounds,
-                                     (uint32_t)c->cu_count * t.waves_per_cu,
+                                     max_waves && max_waves < resident
+                                         ? max_waves
+                                         : resident,
                                      t.unroll, s));
 }
 
@@ -814,6 +817,7 @@ void ms_config_default(ms_config* cfg) {
   cfg->use_graphs = 1;
   cfg->host_chunk_pages = 16384;
   cfg->host_stage_slots = 3;
+  cfg->host_mapped_waves = 128;
 }
 
 const char* ms_status_str(ms_status st) {
@@ -850,6 +854,7 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
   if (cfg.admission_cap_bytes < MS_PAGE_SIZE) return MS_EINVAL;
   if (cfg.host_chunk_pages == 0) cfg.host_chunk_pages = 16384;
   if (cfg.host_stage_slots == 0) cfg.host_stage_slots = 3;
+  if (cfg.host_mapped_waves == 0) cfg.host_mapped_waves = 128;
   if (cfg.host_chunk_pages > 65536 || cfg.host_stage_slots < 2 ||
       cfg.host_stage_slots > 16)
     return MS_EINVAL;
@@ -1327,7 +1332,8 @@ bool ms_internal_resolve_key(ms_ctx* c, ms_key key, uint32_t* slot) {
 ms_status ms_internal_launch_plain(ms_ctx* c, uint32_t key_slot,
                                    const void* src, void* dst,
                                    uint64_t n_pages, const ms_nonce& nonce,
-                                   hipStream_t stream) {
-  return launch_plain_run(c, key_slot, src, dst, n_pages, nonce, stream);
+                                   hipStream_t stream, uint32_t max_waves) {
+  return launch_plain_run(c, key_slot, src, dst, n_pages, nonce, stream,
+                          max_waves);
 }
 HostPath* ms_internal_host_path(ms_ctx* c) { return c->host; }

@@ -50,11 +50,6 @@ namespace {
 
 enum class Where { kDevice, kHost };
 
-// MS_HOST_AUTO picks the staged pipeline for runs of at least this many
-// chunks of at least this many pages.
-constexpr uint64_t kAutoMinChunk = 16384;
-constexpr uint64_t kAutoMinChunks = 8;
-
 struct Buf {
   Where where;
   const uint8_t* host;  // the caller's address
@@ -211,8 +206,13 @@ ms_status run_staged(ms_ctx* c, HostPath* h, uint32_t key_slot,
                                : static_cast<const void*>(src.gpu + off);
     void* kout = stage_out ? static_cast<void*>(buf)
                            : const_cast<uint8_t*>(dst.gpu + off);
+    // a kernel that stores to host memory is bound by the link
+    const uint32_t waves =
+        stage_out || dst.where != Where::kHost
+            ? 0
+            : ms_internal_config(c).host_mapped_waves;
     st = ms_internal_launch_plain(c, key_slot, kin, kout, pages,
-                                  nonce_at(nonce, first), h->s_kernel);
+                                  nonce_at(nonce, first), h->s_kernel, waves);
     if (st) return st;
     if (stage_out) {
       e = hipEventRecord(h->kernel_done[i], h->s_kernel);
@@ -259,23 +259,24 @@ ms_status host_call(ms_ctx* c, ms_key key, const void* src, void* dst,
   }
   uint32_t slot = 0;
   if (!ms_internal_resolve_key(c, key, &slot)) return MS_ENOKEY;
-  if (mode == MS_HOST_AUTO) {
-    // Measured on an MI355X host link (host -> host, 64 MiB chunks): the
-    // staged pipeline passes the mapped kernel from about 8 chunks on
-    // (48 GB/s against 45 at 4 GiB); smaller chunks pay more per chunk than
-    // the overlap gains, and short runs pay the pipeline's fill and drain.
-    const uint64_t chunk = ms_internal_config(c).host_chunk_pages;
-    mode = (chunk >= kAutoMinChunk && n_pages >= kAutoMinChunks * chunk)
-               ? MS_HOST_DMA
-               : MS_HOST_MAPPED;
-  }
+  // Measured on an MI355X host link (host -> host, 1 MiB to 4 GiB): the
+  // mapped kernel with host_mapped_waves = 128 matches or passes the staged
+  // pipeline at every size (49 GB/s against 47-48 from 1 GiB up, 40 against
+  // 25 at 16 MiB) and has the lowest latency.
+  if (mode == MS_HOST_AUTO) mode = MS_HOST_MAPPED;
   const bool stage_in =
       s.where == Where::kHost && (mode == MS_HOST_DMA || mode == MS_HOST_DMA_IN);
   const bool stage_out = d.where == Where::kHost && mode == MS_HOST_DMA;
   hipStream_t caller = ms_internal_stream(c, stream);
-  if (!stage_in && !stage_out)
+  if (!stage_in && !stage_out) {
+    // a kernel that reads or writes host memory is bound by the link, not
+    // by residency: fewer waves keep fewer reads outstanding on it
+    const bool on_link = s.where == Where::kHost || d.where == Where::kHost;
+    const uint32_t waves = on_link ? ms_internal_config(c).host_mapped_waves
+                                   : 0;
     return ms_internal_launch_plain(c, slot, s.gpu, const_cast<uint8_t*>(d.gpu),
-                                    n_pages, *nonce, caller);
+                                    n_pages, *nonce, caller, waves);
+  }
   return run_staged(c, ms_internal_host_path(c), slot, s, d, n_pages, *nonce,
                     stage_in, stage_out, caller);
 }

@@ -25,11 +25,12 @@ ms_status ms_internal_sticky(ms_ctx* c);
 bool ms_internal_resolve_key(ms_ctx* c, ms_key key, uint32_t* slot);
 // One plain launch (split where a launch would exceed its page limit) of
 // n_pages pages from src to dst, both GPU-visible addresses, page p taking
-// the nonce of page p of `nonce`.  No argument checks.
+// the nonce of page p of `nonce`, with at most `max_waves` waves (0 = as
+// many as stay resident).  No argument checks.
 ms_status ms_internal_launch_plain(ms_ctx* c, uint32_t key_slot,
                                    const void* src, void* dst,
                                    uint64_t n_pages, const ms_nonce& nonce,
-                                   hipStream_t stream);
+                                   hipStream_t stream, uint32_t max_waves = 0);
 
 // Owned by host_pages.cpp: created by ms_init, destroyed by ms_shutdown
 // after the device is idle.

@@ -78,7 +78,8 @@ class ms_config(ctypes.Structure):
                 ("use_graphs", ctypes.c_uint32),
                 ("host_chunk_pages", ctypes.c_uint32),
                 ("host_stage_slots", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("host_mapped_waves", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 1)]
 
 
 class ms_resident_config(ctypes.Structure):

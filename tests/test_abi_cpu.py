@@ -79,6 +79,7 @@ def test_host_path_defaults_and_null_context(lib):
     from paper_2004_09252_amd import memshield as ms
     cfg = ms.ms_config_default()
     assert cfg.host_chunk_pages == 16384 and cfg.host_stage_slots == 3
+    assert cfg.host_mapped_waves == 128
     n = ms.linear_nonce(0, 1, 0)
     assert ms.ms_encrypt_host_pages(None, 1, None, None, 1, n, 0) == \
         ms.MS_EINVAL

@@ -325,9 +325,9 @@ def test_host_alloc_is_zeroed_and_mapped(ms, eng):
 
 
 def test_large_run_sampled_against_oracle(ms):
-    """512 MiB of host pages (8 default chunks: MS_HOST_AUTO takes the staged
-    pipeline) through every mode, one call each, with a deterministic sample
-    of pages checked against the oracle."""
+    """512 MiB of host pages (8 default staging chunks) through every mode,
+    one call each, with a deterministic sample of pages checked against the
+    oracle."""
     _note("large host run 131072 pages")
     n = 131072
     with ms.Engine(0) as e:
