@@ -281,7 +281,12 @@ ms_status ms_autotune(ms_ctx *ctx, uint64_t n_pages, ms_tuning *out);
 /* Current tuning for a batch of n_pages (tuned or default). */
 ms_status ms_get_tuning(ms_ctx *ctx, uint64_t n_pages, ms_tuning *out);
 
-/* Force a tuning for every bucket (tests and sweeps); NULL restores tuning. */
+/*
+ * Force a tuning for every bucket (tests and sweeps); NULL restores tuning.
+ * While a tuning is forced, the serving scheduler runs every batch with the
+ * fused kernel and that tuning, also a batch of a single request (which it
+ * otherwise runs with the plain kernel).
+ */
 ms_status ms_set_tuning(ms_ctx *ctx, const ms_tuning *t);
 
 ms_status ms_get_stats(ms_ctx *ctx, ms_stats *out);

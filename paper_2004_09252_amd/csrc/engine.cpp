@@ -484,6 +484,11 @@ bool reap(ms_ctx* c) {
 
 // Form and launch one batch from the queues; returns false if nothing
 // could be launched.
+bool tuning_forced(ms_ctx* c) {
+  std::lock_guard<std::mutex> lk(c->tune_mu);
+  return c->forced;
+}
+
 bool launch_one(ms_ctx* c) {
   if (c->serve_free.empty()) return false;
   std::vector<Pending> take;
@@ -542,8 +547,9 @@ bool launch_one(ms_ctx* c) {
   c->st_pf_issued.fetch_add(n_pf);
   ms_status st = MS_OK;
   hipStream_t strm = c->serve_streams[stream_i];
-  if (copy && take.size() == 1) {
-    // a batch of one request needs no descriptors: plain launch
+  if (copy && take.size() == 1 && !tuning_forced(c)) {
+    // a batch of one request needs no descriptors: plain launch (unless a
+    // caller has forced the fused launch's tuning for every batch)
     const ms_request& r = take[0].req;
     ms::PlainArgs a;
     a.keys = c->d_keys;

@@ -122,43 +122,23 @@ def test_alone_equals_mix_equals_oracle(ms):
 
 def test_batches_overlap_on_device(ms):
     """Requests that arrive while a large batch runs are launched as their
-    own batches on other streams and complete before the large one."""
-    _note("overlap")
-    eng = ms.Engine(0)
-    try:
-        r = _Reqs(ms, eng, seed=42, n=8, max_pages=2)
-        import torch
-        # warm up: kernels loaded, streams created
-        t = eng.submit([r.req(7, r.dst_b)])
-        assert eng.poll(t, timeout_s=30)[0] == 0
-        big_pages = 65536
-        big = torch.zeros(big_pages * 4096, dtype=torch.uint8, device="cuda")
-        torch.cuda.synchronize()
-        # a narrow grid for the large request leaves room on the chip
-        assert ms.ms_set_tuning(eng.ctx, ms.ms_tuning(64, 1, 2, 0, 0.0)) == 0
-        before = eng.stats().batches
-        tb = eng.submit([ms.request(r.keys[0], big, big, big_pages,
-                                    ms.linear_nonce(0, 1, 0))])
-        t0 = time.time()
-        while eng.stats().batches == before and time.time() - t0 < 10:
-            pass
-        overlapped = 0
-        for i in range(6):
-            ts = eng.submit([r.req(i, r.dst_a)])
-            st, d_small = eng.poll(ts, timeout_s=30)
-            assert st == 0 and d_small == [1]
-            st2, d_big = eng.poll(tb, timeout_s=0)
-            overlapped += d_big == [0]
-        stats = eng.stats()
-        st, _ = eng.poll(tb, timeout_s=30)
-        assert st == 0
-        assert stats.max_inflight_batches >= 2
-        assert overlapped >= 1, "no small request finished during the big one"
-        for i in range(6):
-            assert np.array_equal(r.slice(r.dst_a, i), r.expect(i))
-    finally:
-        ms.ms_set_tuning(eng.ctx, None)
-        eng.close()
+    own batches on other streams and complete before the large one.  This
+    needs the engine's serving streams on distinct hardware queues, which
+    the HIP runtime does not promise in a process that already holds many
+    streams (it shares its few queues among them); the scenario therefore
+    runs in a fresh child process whose first streams are the engine's."""
+    _note("overlap (child process)")
+    import json
+    import subprocess
+    child = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                         "serving_overlap_child.py")
+    r = subprocess.run([sys.executable, "-u", child], capture_output=True,
+                       text=True, timeout=180)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["small_exact"]
+    assert out["max_inflight_batches"] >= 2
+    assert out["overlapped"] >= 1, out
 
 
 def test_admission_cap_bounds_inflight_bytes(ms):
