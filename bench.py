@@ -166,6 +166,56 @@ def run_bulk(args, ms, torch, b):
     return dt, launch_ms
 
 
+def run_variants(args, ms, torch, b):
+    """Reduced-round ChaCha (12 and 8 rounds) on the bulk workload: fewer
+    integer operations per byte move the kernel from the ALU roof toward
+    the HBM roof.  Each row: data GB/s of one encrypt pass, the ALU fraction
+    (rounds*48 + 32 operations per 64-byte block) and the HBM fraction
+    (2 bytes moved per data byte)."""
+    import numpy as np
+    import oracle
+    n = b.data.shape[0]
+    src = torch.from_numpy(b.data.reshape(-1)).to("cuda")
+    dst = torch.empty_like(src)
+    nonce = ms.linear_nonce(b.nonce_base, b.nonce_stride, b.nonce_tag)
+    stream = torch.cuda.current_stream()
+    sample = [0, n // 3, n - 1]
+    out = {}
+    for rounds in (20, 12, 8):
+        eng = ms.Engine(0, rounds=rounds)
+        key = eng.key_load(b.key)
+        for _ in range(20):
+            eng.encrypt_pages(key, src, dst, nonce, stream=stream)
+        reps = 100
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            eng.encrypt_pages(key, src, dst, nonce, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / reps
+        want = oracle.cipher_pages(
+            b.key, np.stack([np.frombuffer(oracle.nonce_linear(
+                i, b.nonce_base, b.nonce_stride, b.nonce_tag), np.uint8)
+                for i in sample]), b.data[sample], rounds=rounds)
+        got = dst.view(n, 4096)[sample].cpu().numpy()
+        if not np.array_equal(got, want):
+            raise RuntimeError("ChaCha%d differs from the oracle" % rounds)
+        ops = (rounds * 48 + 32) * 64.0 * n
+        out["chacha%d" % rounds] = {
+            "data_GBps": round(n * 4096 / t / 1e9, 1),
+            "ms_per_GiB": round(t * 1e3, 4),
+            "alu_frac": round(ops / t / MI355X_INT32_VALU_OPS, 4),
+            "hbm_frac": round(2 * n * 4096 / t / MI355X_HBM_BYTES, 4),
+            "ops_per_byte": round((rounds * 48 + 32) / 64.0, 2)}
+        eng.key_destroy(key)
+        eng.close()
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batched(args, ms, torch):
     """Fused batched launch (graph replay) vs 512 plain launches."""
     import numpy as np
@@ -663,6 +713,7 @@ def main():
                     help="skip both host-memory page paths (host_resident "
                          "and resident_key)")
     ap.add_argument("--no-resident", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--host-only", action="store_true",
                     help="run only the host-resident section and print its "
                          "JSON (for profiling that path alone)")
@@ -736,6 +787,9 @@ def main():
     }
     log("calibration probes")
     line["calibration"] = calibrate(ms, torch)
+    if not args.no_variants:
+        log("reduced-round variants")
+        line["cipher_variants"] = run_variants(args, ms, torch, b)
     if not args.no_batched:
         log("batched workload")
         line["batched"] = run_batched(args, ms, torch)

@@ -126,7 +126,9 @@ typedef struct ms_config {
     uint32_t host_mapped_waves;   /* kernels that read or write host pages:
                                      at most this many waves, so that few
                                      reads wait on the link (default 128) */
-    uint32_t reserved[1];
+    uint32_t serve_spin_us;       /* the scheduler polls this long after its
+                                     last work before it sleeps until the
+                                     next submission (default 5000) */
 } ms_config;
 
 /* Tunables of the fused batched launch, chosen by ms_autotune. */

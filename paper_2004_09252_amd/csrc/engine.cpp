@@ -144,11 +144,15 @@ struct ms_ctx {
   std::atomic<bool> stop{false};
   std::thread scheduler;
 
+  // serve_slots, serve_free, inflight and inflight_bytes belong to whoever
+  // holds sched_mu: the scheduler thread, or a submitting thread that finds
+  // the lock free and launches its own batch at once
+  std::mutex sched_mu;
   std::vector<BatchSlot> serve_slots;
   std::vector<hipStream_t> serve_streams;
   std::vector<int> serve_free;
   std::deque<InflightBatch> inflight;
-  uint64_t inflight_bytes = 0;  // scheduler thread only (mirrored in stats)
+  uint64_t inflight_bytes = 0;  // under sched_mu (mirrored in stats)
 
   std::atomic<int32_t> sticky_error{0};
 
@@ -589,8 +593,13 @@ void scheduler_main(ms_ctx* c) {
   (void)hipSetDevice(c->device);
   auto last_work = Clock::now();
   for (;;) {
-    bool did = reap(c);
-    while (launch_one(c)) did = true;
+    bool did = false, idle_device = false;
+    {
+      std::lock_guard<std::mutex> lk(c->sched_mu);
+      did = reap(c);
+      while (launch_one(c)) did = true;
+      idle_device = c->inflight.empty();
+    }
     if (did) {
       last_work = Clock::now();
       continue;
@@ -600,8 +609,8 @@ void scheduler_main(ms_ctx* c) {
       std::lock_guard<std::mutex> lk(c->q_mu);
       queues_empty = c->demand_q.empty() && c->prefetch_q.empty();
     }
-    if (c->stop.load() && queues_empty && c->inflight.empty()) break;
-    if (!c->inflight.empty()) {
+    if (c->stop.load() && queues_empty && idle_device) break;
+    if (!idle_device) {
       // work on the device: poll its completion closely
       std::this_thread::yield();
       continue;
@@ -612,8 +621,10 @@ void scheduler_main(ms_ctx* c) {
       std::this_thread::yield();
       continue;
     }
-    // idle: spin briefly for low latency, then sleep until a submission
-    if (Clock::now() - last_work < std::chrono::microseconds(200)) {
+    // idle: keep polling for a while (a thread woken from a sleep costs
+    // tens of microseconds), then sleep until a submission
+    if (Clock::now() - last_work <
+        std::chrono::microseconds(c->cfg.serve_spin_us)) {
       std::this_thread::yield();
       continue;
     }
@@ -723,6 +734,21 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
       (prefetch ? c->prefetch_q : c->demand_q).push_back(p);
     }
   }
+  if (!prefetch) {
+    // direct launch on an idle device: if no batch is in flight and the
+    // scheduler is not busy, form and launch the batch on this thread,
+    // which saves the hop to the scheduler thread at low load.  Under load
+    // (batches in flight) requests queue and the scheduler batches them.
+    // Completions are always reaped by the scheduler.
+    std::unique_lock<std::mutex> lk(c->sched_mu, std::try_to_lock);
+    if (lk.owns_lock() && c->inflight.empty()) {
+      int prev = c->device;
+      (void)hipGetDevice(&prev);
+      if (prev != c->device) (void)hipSetDevice(c->device);
+      (void)launch_one(c);
+      if (prev != c->device) (void)hipSetDevice(prev);
+    }
+  }
   c->q_cv.notify_one();
   if (!prefetch) c->st_submitted.fetch_add(n);
   if (tickets_out)
@@ -824,6 +850,7 @@ void ms_config_default(ms_config* cfg) {
   cfg->host_chunk_pages = 16384;
   cfg->host_stage_slots = 3;
   cfg->host_mapped_waves = 128;
+  cfg->serve_spin_us = 5000;
 }
 
 const char* ms_status_str(ms_status st) {

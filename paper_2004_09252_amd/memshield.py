@@ -79,7 +79,7 @@ class ms_config(ctypes.Structure):
                 ("host_chunk_pages", ctypes.c_uint32),
                 ("host_stage_slots", ctypes.c_uint32),
                 ("host_mapped_waves", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 1)]
+                ("serve_spin_us", ctypes.c_uint32)]
 
 
 class ms_resident_config(ctypes.Structure):
