@@ -648,10 +648,15 @@ def run_prefetch(args, ms, torch):
                 return False
         return True
 
-    runs = (("baseline_window_W_plus_P", W + P, 0, False, 0.0),
-            ("predictor_window_W_prefetch_P", W, P, True, 0.0),
-            ("predictor_min_prob", W, P, True, args.prefetch_min_prob))
-    for name, window, slots, use, min_prob in runs:
+    # background pre-encryption (encrypt-side twin of the prefetcher):
+    # threshold 4 of W+P = 16 window slots, alone and with the gated predictor
+    runs = (("baseline_window_W_plus_P", W + P, 0, False, 0.0, 0),
+            ("predictor_window_W_prefetch_P", W, P, True, 0.0, 0),
+            ("predictor_min_prob", W, P, True, args.prefetch_min_prob, 0),
+            ("background_pre_encryption", W + P, 0, False, 0.0, 4),
+            ("predictor_min_prob_and_background", W, P, True,
+             args.prefetch_min_prob, 4))
+    for name, window, slots, use, min_prob, bg in runs:
         log("prefetch run: %s" % name)
         mem = prefetch.PagedMemory(eng, keys, tr.pages_per_client,
                                    slots=W + P + 32)
@@ -660,12 +665,15 @@ def run_prefetch(args, ms, torch):
         cnt, _, dec, cl = prefetch.run(
             tr, window, mem=mem, prefetch_slots=slots,
             predictor=pred if use else None, vocab=vocab if use else None,
-            k=8, predict_from=split, count_from=split, min_prob=min_prob)
+            k=8, predict_from=split, count_from=split, min_prob=min_prob,
+            bg_threshold=bg)
         prefetch.finish(mem, cl)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         r = dict(cnt)
         r["decrypt_fault_rate"] = round(cnt["faults"] / cnt["accesses"], 5)
+        if bg:
+            r["bg_threshold"] = bg
         if use:
             r["min_prob"] = min_prob
             r["prefetch_precision"] = round(
@@ -677,8 +685,17 @@ def run_prefetch(args, ms, torch):
         out[name] = r
         del mem
         torch.cuda.empty_cache()
-    b = out["baseline_window_W_plus_P"]["faults"]
-    for name in ("predictor_window_W_prefetch_P", "predictor_min_prob"):
+    base = out["baseline_window_W_plus_P"]
+    for name in ("background_pre_encryption",
+                 "predictor_min_prob_and_background"):
+        r = out[name]
+        r["fault_path_encrypts_removed_frac"] = round(
+            1 - r["encrypts"] / max(base["encrypts"], 1), 4)
+        r["encrypt_work_vs_baseline"] = round(
+            (r["encrypts"] + r["encrypts_bg"]) / max(base["encrypts"], 1), 3)
+    b = base["faults"]
+    for name in ("predictor_window_W_prefetch_P", "predictor_min_prob",
+                 "predictor_min_prob_and_background"):
         p = out[name]["faults"]
         out[name]["decrypt_faults_removed_frac"] = round(1 - p / max(b, 1), 4)
         out[name]["gpu_decrypts_vs_baseline"] = round(

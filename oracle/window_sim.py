@@ -19,6 +19,18 @@ pushed out of the prefetch FIFO unused is dropped without re-encryption (it
 was never modified).  Writes: an access may XOR a 64-bit value into one
 8-byte word of its page.
 
+Background pre-encryption (the paper's conclusions, section 7, suggest
+encrypting window pages in the background once the free slots of the window
+fall below a threshold).  Reading: a window page is "clean" when a
+background encryption has stored its current contents; a clean page can be
+evicted without encrypting it on the fault path.  The reclaimable slots of a
+window are its free slots plus its clean pages.  After each window miss,
+while the reclaimable slots are fewer than `bg_threshold`, the oldest page
+that is not clean is encrypted in the background and becomes clean (it
+stays in the window, in clear).  A write to a clean page makes it dirty
+again (that background encryption was wasted).  An evicted dirty page is
+encrypted on the fault path as without the mechanism.
+
 ``simulate`` counts faults, first touches, decrypts and encrypts for a trace
 and a given sequence of prefetch decisions; ``final_plaintext`` computes the
 page contents every write sequence leads to, independent of the window.
@@ -31,37 +43,56 @@ import numpy as np
 
 
 def simulate(pages, window: int, prefetch=None, prefetch_slots: int = 0,
-             start: int = 0, stop: int | None = None):
+             start: int = 0, stop: int | None = None, writes=None,
+             bg_threshold: int = 0):
     """One client's accesses `pages` (sequence of page ids).
 
     `prefetch`: optional dict {access index t: list of page ids} of pages the
     prefetcher asks for right after access t is served (already-clear pages
-    are ignored).  Counters are taken over accesses [start, stop).
+    are ignored).  `writes`: optional sequence, true where access t writes
+    its page.  `bg_threshold`: background pre-encryption threshold (0 = no
+    background encryption).  Counters are taken over accesses [start, stop).
     Returns a dict of counters and the ordered list of fault events
-    (t, page) in [start, stop) that needed a decrypt.
+    (t, page) in [start, stop) that needed a decrypt.  "encrypts" counts
+    encryptions on the fault path (evictions of pages that are not clean),
+    "encrypts_bg" background encryptions, "bg_wasted" clean pages written
+    again, "evict_clean" evictions that needed no encryption.
     """
     stop = len(pages) if stop is None else stop
-    win = OrderedDict()          # page -> None, oldest first
+    win = OrderedDict()          # page -> clean (bool), oldest first
     pf = OrderedDict()           # prefetched, unused pages
     touched = set()
     cnt = {"accesses": 0, "faults": 0, "first_touch": 0, "decrypts": 0,
            "encrypts": 0, "prefetch_issued": 0, "prefetch_hits": 0,
-           "prefetch_wasted": 0}
+           "prefetch_wasted": 0, "encrypts_bg": 0, "bg_wasted": 0,
+           "evict_clean": 0}
     fault_log = []
 
     def admit(p, counting):
-        win[p] = None
+        win[p] = False
         if len(win) > window:
-            old, _ = win.popitem(last=False)
+            old, clean = win.popitem(last=False)
             if counting:
-                cnt["encrypts"] += 1
+                cnt["evict_clean" if clean else "encrypts"] += 1
+
+    def background(counting):
+        reclaimable = window - len(win) + sum(1 for c in win.values() if c)
+        for q in win:
+            if reclaimable >= bg_threshold:
+                break
+            if not win[q]:
+                win[q] = True
+                reclaimable += 1
+                if counting:
+                    cnt["encrypts_bg"] += 1
 
     for t in range(stop):
         p = int(pages[t])
         counting = t >= start
         if counting:
             cnt["accesses"] += 1
-        if p in win:
+        miss = p not in win
+        if not miss:
             pass
         elif p in pf:
             del pf[p]
@@ -79,6 +110,12 @@ def simulate(pages, window: int, prefetch=None, prefetch_slots: int = 0,
                 if counting:
                     cnt["first_touch"] += 1
             admit(p, counting)
+        if writes is not None and writes[t] and win[p]:
+            win[p] = False
+            if counting:
+                cnt["bg_wasted"] += 1
+        if bg_threshold > 0 and miss:
+            background(counting)
         if prefetch and t in prefetch:
             for q in prefetch[t]:
                 q = int(q)

@@ -21,6 +21,14 @@ Fault events (window misses) are what the server observes, with or without
 prefetching, so the predictor's input sequence is the same in training and
 in use.
 
+Background pre-encryption (the paper's conclusions suggest it as future
+work): after each window miss, while a client's reclaimable slots (free
+slots plus "clean" pages, whose current contents a background encryption
+has already stored) are fewer than `bg_threshold`, its oldest page that is
+not clean is encrypted in the background and stays in the window.  A clean
+page is evicted without an encryption on the fault path; a write makes it
+dirty again.
+
 GPU work is queued and flushed in fused launches; a flush happens before any
 operation that would conflict with one already queued (a page read and
 written in one launch, a slot reused, a write that must follow a fill or
@@ -183,26 +191,30 @@ class Client:
     pf: OrderedDict           # prefetched unused page -> slot
     touched: bytearray
     events: deque             # recent fault-event pages
+    clean: set = dataclasses.field(default_factory=set)  # window pages
+    # whose current contents a background encryption has stored
 
 
 def new_counters():
     return {"accesses": 0, "faults": 0, "first_touch": 0, "decrypts": 0,
             "encrypts": 0, "prefetch_issued": 0, "prefetch_hits": 0,
-            "prefetch_wasted": 0, "events": 0}
+            "prefetch_wasted": 0, "events": 0, "encrypts_bg": 0,
+            "bg_wasted": 0, "evict_clean": 0}
 
 
 def run(trace, window: int, mem: PagedMemory | None = None,
         prefetch_slots: int = 0, predictor=None, vocab: DeltaVocab | None = None,
         k: int = 8, predict_from: int = 0, stop: int | None = None,
         count_from: int = 0, record_events: bool = False,
-        min_prob: float = 0.0):
+        min_prob: float = 0.0, bg_threshold: int = 0):
     """Replay `trace` (workloads.AccessTrace) for steps [0, stop) with all
     clients in lockstep.  Prediction is active for steps >= predict_from,
     counters cover steps >= count_from.  Returns (counters, events, decisions)
     where events[c] is the list of fault-event pages of client c (if
     recorded) and decisions maps (c, t) to the pages the predictor asked
     for after step t.  Of the predictor's top-k deltas only those with a
-    softmax probability of at least `min_prob` are pre-decrypted."""
+    softmax probability of at least `min_prob` are pre-decrypted.
+    `bg_threshold` > 0 turns on background pre-encryption (module doc)."""
     C = trace.clients
     n = trace.pages_per_client
     stop = trace.steps if stop is None else stop
@@ -218,11 +230,27 @@ def run(trace, window: int, mem: PagedMemory | None = None,
         cl.win[p] = s
         if len(cl.win) > window:
             q, sq = cl.win.popitem(last=False)
+            clean = q in cl.clean
+            cl.clean.discard(q)
             if mem is not None:
-                mem.encrypt(c, sq, q)
+                if not clean:
+                    mem.encrypt(c, sq, q)
                 mem.release(c, sq)
             if counting:
-                cnt["encrypts"] += 1
+                cnt["evict_clean" if clean else "encrypts"] += 1
+
+    def background(c, cl, counting):
+        reclaimable = window - len(cl.win) + len(cl.clean)
+        for q, sq in cl.win.items():
+            if reclaimable >= bg_threshold:
+                break
+            if q not in cl.clean:
+                cl.clean.add(q)
+                if mem is not None:
+                    mem.encrypt(c, sq, q)
+                reclaimable += 1
+                if counting:
+                    cnt["encrypts_bg"] += 1
 
     for t in range(stop):
         counting = t >= count_from
@@ -233,7 +261,8 @@ def run(trace, window: int, mem: PagedMemory | None = None,
             if counting:
                 cnt["accesses"] += 1
             s = cl.win.get(p)
-            if s is None:
+            miss = s is None
+            if miss:
                 # fault event: the server sees it
                 if counting:
                     cnt["events"] += 1
@@ -264,8 +293,15 @@ def run(trace, window: int, mem: PagedMemory | None = None,
                         len(cl.events) == ctx + 1:
                     want.append(c)
             v = int(value[c, t])
-            if v and mem is not None:
-                mem.write(c, s, int(word[c, t]), v)
+            if v:
+                if mem is not None:
+                    mem.write(c, s, int(word[c, t]), v)
+                if p in cl.clean:
+                    cl.clean.discard(p)
+                    if counting:
+                        cnt["bg_wasted"] += 1
+            if bg_threshold > 0 and miss:
+                background(c, cl, counting)
         if want:
             hist = np.array([list(clients[c].events) for c in want],
                             dtype=np.int64)
@@ -308,12 +344,15 @@ def run(trace, window: int, mem: PagedMemory | None = None,
 
 def finish(mem: PagedMemory, clients) -> None:
     """Encrypt every page still in a window back into the store (the end of
-    the run); unused prefetched pages are dropped."""
+    the run) unless a background encryption already stored it; unused
+    prefetched pages are dropped."""
     for c, cl in enumerate(clients):
         for p, s in cl.win.items():
-            mem.encrypt(c, s, p)
+            if p not in cl.clean:  # clean pages are already stored
+                mem.encrypt(c, s, p)
         cl.win.clear()
         cl.pf.clear()
+        cl.clean.clear()
     mem.flush()
 
 

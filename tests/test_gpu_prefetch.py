@@ -45,14 +45,17 @@ def _check_store(mem, tr, key_bytes, stop):
         assert not store[c][~touched].any()
 
 
-def _oracle_counts(tr, window, start, stop, decisions=None, slots=0):
+def _oracle_counts(tr, window, start, stop, decisions=None, slots=0,
+                   bg_threshold=0):
     tot = {}
     for c in range(tr.clients):
         pf = None
         if decisions is not None:
             pf = {t: q for (cc, t), q in decisions.items() if cc == c}
         o, _ = window_sim.simulate(tr.page[c, :stop], window, prefetch=pf,
-                                   prefetch_slots=slots, start=start)
+                                   prefetch_slots=slots, start=start,
+                                   writes=tr.value[c, :stop] != 0,
+                                   bg_threshold=bg_threshold)
         for k, v in o.items():
             tot[k] = tot.get(k, 0) + v
     return tot
@@ -110,6 +113,34 @@ def test_predictor_run_counts_and_store_bit_exact():
         for k, v in ref.items():
             assert cnt[k] == v, k
         assert cnt["prefetch_issued"] > 0 and cnt["prefetch_hits"] > 0
+        _check_store(mem, tr, kb, tr.steps)
+    finally:
+        eng.close()
+
+
+@pytest.mark.parametrize("threshold", [1, 3])
+def test_background_pre_encryption_store_bit_exact(threshold):
+    """Background pre-encryption on GPU-resident page data: the counters
+    equal the oracle's, evictions of clean pages skip the fault-path
+    encryption, and the final ciphertext store is the oracle's, bit for
+    bit (a background encryption followed by a write is redone at
+    eviction)."""
+    _note("background pre-encryption threshold=%d" % threshold)
+    from paper_2004_09252_amd import memshield as ms
+    from paper_2004_09252_amd import prefetch
+    tr = workloads.access_trace(seed=23, total_pages=16 * 256,
+                                accesses=16 * 1500, clients=16)
+    kb = _keys(tr, 23)
+    eng = ms.Engine(0)
+    try:
+        keys = [eng.key_load(k) for k in kb]
+        mem = prefetch.PagedMemory(eng, keys, tr.pages_per_client, slots=40)
+        cnt, _, _, cl = prefetch.run(tr, 6, mem=mem, bg_threshold=threshold)
+        prefetch.finish(mem, cl)
+        ref = _oracle_counts(tr, 6, 0, tr.steps, bg_threshold=threshold)
+        for k, v in ref.items():
+            assert cnt[k] == v, k
+        assert cnt["evict_clean"] > 0 and cnt["encrypts_bg"] > 0
         _check_store(mem, tr, kb, tr.steps)
     finally:
         eng.close()

@@ -80,3 +80,74 @@ def test_delta_vocab_and_examples():
     x, y = prefetch.training_examples(ev, vocab, context=3)
     assert x.tolist() == [[0, 0, 0], [0, 0, 0], [0, 0, 1]]
     assert y.tolist() == [0, 1, 1]
+
+
+def test_background_pre_encryption_hand_cases():
+    """Background pre-encryption (the paper's conclusions suggest it): after
+    each window miss, while free slots + clean pages < threshold, the oldest
+    page that is not clean is encrypted in the background."""
+    # W=2, threshold 1, no writes: every eviction finds its page clean
+    cnt, _ = window_sim.simulate([0, 1, 2, 0], window=2, bg_threshold=1,
+                                 writes=[0, 0, 0, 0])
+    # t1: {0,1} full, 0 encrypted in background; t2: 0 evicted clean, 1
+    # encrypted; t3 (fault on 0): 1 evicted clean, 2 encrypted
+    assert cnt["encrypts"] == 0 and cnt["evict_clean"] == 2
+    assert cnt["encrypts_bg"] == 3 and cnt["bg_wasted"] == 0
+    assert cnt["faults"] == 1 and cnt["first_touch"] == 3
+    # a write to a clean page undoes its background encryption
+    cnt, _ = window_sim.simulate([0, 1, 0, 2], window=2, bg_threshold=1,
+                                 writes=[0, 0, 1, 0])
+    # t1: 0 encrypted in background; t2: 0 written (wasted); t3: 0 evicted
+    # dirty (encrypted on the fault path), 1 encrypted in background
+    assert cnt["encrypts"] == 1 and cnt["evict_clean"] == 0
+    assert cnt["encrypts_bg"] == 2 and cnt["bg_wasted"] == 1
+    # a write to a page that is not clean costs nothing extra
+    cnt, _ = window_sim.simulate([0, 1, 1, 2], window=2, bg_threshold=1,
+                                 writes=[0, 0, 1, 0])
+    assert cnt["encrypts"] == 0 and cnt["evict_clean"] == 1
+    assert cnt["encrypts_bg"] == 2 and cnt["bg_wasted"] == 0
+
+
+def test_background_pre_encryption_invariants():
+    """On a mixed trace, for several thresholds: the window's behaviour
+    (faults, first touches, decrypts, evictions) does not change; every
+    eviction is either clean or encrypted on the fault path; every
+    background encryption ends clean-evicted, wasted by a write, or still
+    clean in the window at the end."""
+    tr = workloads.access_trace(seed=12, accesses=8 * 3000, clients=8,
+                                total_pages=8 * 256)
+    for c in range(tr.clients):
+        pages = tr.page[c]
+        writes = tr.value[c] != 0
+        base, _ = window_sim.simulate(pages, 6)
+        assert base["encrypts_bg"] == 0 and base["evict_clean"] == 0
+        same, _ = window_sim.simulate(pages, 6, writes=writes, bg_threshold=0)
+        assert same == base
+        for thr in (1, 2, 4, 6, 9):
+            cnt, log = window_sim.simulate(pages, 6, writes=writes,
+                                           bg_threshold=thr)
+            for k in ("faults", "first_touch", "decrypts", "accesses"):
+                assert cnt[k] == base[k], (thr, k)
+            assert cnt["encrypts"] + cnt["evict_clean"] == base["encrypts"]
+            left = cnt["encrypts_bg"] - cnt["evict_clean"] - cnt["bg_wasted"]
+            assert 0 <= left <= 6, (thr, left)
+            # a larger threshold never puts more encryptions on the fault path
+            if thr > 1:
+                assert cnt["encrypts"] <= prev["encrypts"], thr
+            prev = cnt
+
+
+def test_product_host_logic_matches_oracle_with_background():
+    tr = workloads.access_trace(seed=13, accesses=8 * 2000, clients=8,
+                                total_pages=8 * 256)
+    for thr in (1, 3):
+        cnt, _, _, _ = prefetch.run(tr, 6, count_from=300, bg_threshold=thr)
+        tot = {}
+        for c in range(tr.clients):
+            o, _ = window_sim.simulate(tr.page[c], 6, start=300,
+                                       writes=tr.value[c] != 0,
+                                       bg_threshold=thr)
+            for k, v in o.items():
+                tot[k] = tot.get(k, 0) + v
+        for k, v in tot.items():
+            assert cnt[k] == v, (thr, k)
