@@ -780,6 +780,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
+        "paper_context": {
+            "hardware": "Intel Core i7-4771 + NVIDIA GeForce GTX 970 (CUDA 10.1)",
+            "published_page_cipher_GBps": None,
+            "note": "the paper reports whole-application wall-clock times "
+                    "only (e.g. aes 35.23 s vs 0.30 s unprotected at a "
+                    "4-page window); no page-cipher throughput to compare"},
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "bulk: %d pages x 4 KiB (%.2f GiB) uniform "
