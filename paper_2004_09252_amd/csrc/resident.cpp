@@ -502,9 +502,12 @@ ms_status ms_resident_poll(ms_resident* r, const ms_ticket* tickets, size_t n,
     }
     if (pending == 0) return MS_OK;
     if (timeout_ns == 0 || Clock::now() >= deadline) return MS_ETIMEDOUT;
-    // a waiting host counts as activity for the kernel's idle limit
-    if ((++beat & 1023) == 0)
+    // a waiting host counts as activity for the kernel's idle limit; spin
+    // on host memory, giving the core away now and then
+    if ((++beat & 1023) == 0) {
       __atomic_fetch_add(&r->hctl->heartbeat, 1, __ATOMIC_RELAXED);
+      std::this_thread::yield();
+    }
   }
 }
 

@@ -545,6 +545,12 @@ class HostBuffer:
         if self.ptr and self.engine.ctx:
             self.array = None
             _check(ms_host_free(self.engine.ctx, self.ptr), "ms_host_free")
+        self.array = None
+        self.ptr = 0
+
+    def _invalidate(self):
+        # the engine's shutdown freed (and zeroed) the memory
+        self.array = None
         self.ptr = 0
 
 
@@ -623,6 +629,7 @@ class Engine:
             setattr(cfg, k, v)
         self.device = device
         self._residents = []
+        self._host_buffers = weakref.WeakSet()
         st, self.ctx = ms_init(device, cfg)
         _check(st, "ms_init")
         _live_engines.add(self)
@@ -633,6 +640,8 @@ class Engine:
                 r.stop()
             ms_shutdown(self.ctx)
             self.ctx = None
+            for b in list(self._host_buffers):
+                b._invalidate()
 
     def __enter__(self):
         return self
@@ -688,7 +697,9 @@ class Engine:
     def host_alloc(self, nbytes: int) -> HostBuffer:
         st, p = ms_host_alloc(self.ctx, nbytes)
         _check(st, "ms_host_alloc")
-        return HostBuffer(self, p, nbytes)
+        b = HostBuffer(self, p, nbytes)
+        self._host_buffers.add(b)
+        return b
 
     def _host_pages(self, fn, name, key, src, dst, nonce, n_pages, mode,
                     stream):
