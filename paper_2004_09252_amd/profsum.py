@@ -63,14 +63,15 @@ def trace(db_path: str, out_path: str, cmd: str) -> None:
         lines.append("| %s | %d | %d | %.2f | %.2f | %.2f |" % (
             _short(name), blocks, len(d), sum(d) / len(d) / 1e3,
             min(d) / 1e3, max(d) / 1e3))
+    # the top_kernels view reports microseconds (the kernels table, ns)
     lines += ["", "rocprofv3 --stats (all dispatches of a kernel together):",
-              "", "| kernel | calls | total us | avg us | % |",
+              "", "| kernel | calls | total ms | avg us | % |",
               "|---|---|---|---|---|"]
     for name, calls, total, avg, pct in db.execute(
             "select name, total_calls, total_duration, average, percentage "
             "from top_kernels limit 12"):
-        lines.append("| %s | %d | %.1f | %.2f | %.1f |" % (
-            _short(name), calls, total / 1e3, avg / 1e3, pct))
+        lines.append("| %s | %d | %.2f | %.2f | %.1f |" % (
+            _short(name), calls, total / 1e3, avg, pct))
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
 
