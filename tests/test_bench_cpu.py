@@ -1,0 +1,73 @@
+"""CPU checks of the measurement tooling: the bench's one-GPU contract and
+constants, the committed traffic summary belonging to the current kernel
+sources, and the arithmetic of the rocprofv3 summaries on a small synthetic
+result database."""
+import os
+import sqlite3
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_bench_algorithmic_constants():
+    import bench
+    # 20 rounds x 4 quarter rounds x 12 add/xor/rotate + 16 feed-forward
+    # adds + 16 data XORs per 64-byte block
+    assert bench.OPS_PER_BLOCK == 992
+    assert bench.OPS_PER_PAGE == 992 * 64
+    assert bench.HBM_BYTES_PER_PAGE == 8192
+    assert abs(bench.MI355X_INT32_VALU_OPS - 256 * 64 * 2.4e9) < 1
+    assert abs(bench.PCIE_GEN5_X16_GBPS - 63.0) < 0.1
+
+
+def test_committed_traffic_summary_matches_kernel_sources():
+    """bench.py reports roofline.traffic only while the counters in
+    profiles/ were taken on the current kernel sources."""
+    import bench
+    t = bench.read_traffic()
+    assert t is not None, "kernel sources changed since the counters"
+    assert abs(t / (2 * 262144 * 4096) - 1) < 0.01
+
+
+def _db(path, rows):
+    db = sqlite3.connect(path)
+    db.execute("create table counters_collection (kernel_name text, "
+               "counter_name text, value real, duration real)")
+    db.executemany("insert into counters_collection values (?, ?, ?, ?)",
+                   rows)
+    db.commit()
+    db.close()
+
+
+def test_traffic_calibration_arithmetic(tmp_path):
+    from paper_2004_09252_amd import profsum
+    k = "void ms::(anonymous namespace)::" + profsum.BULK_KERNEL + "(args)"
+    c = "ms::(anonymous namespace)::copy_probe_kernel(a, b, c)"
+    # the fetch counter reads half of the copy's known 1 GiB, the write
+    # counter all of it; the kernel moves 2 GiB (1 in, 1 out) at 1.5x
+    _db(tmp_path / "f.db", [(k, "FETCH_SIZE", 1.5 * 524288, 1.0),
+                            (c, "FETCH_SIZE", 524288, 1.0)])
+    _db(tmp_path / "w.db", [(k, "WRITE_SIZE", 1048576, 1.0),
+                            (c, "WRITE_SIZE", 1048576, 1.0)])
+    out = tmp_path / "t.txt"
+    profsum.traffic(str(tmp_path / "f.db"), str(tmp_path / "w.db"), str(out),
+                    "cmd f", "cmd w")
+    vals = dict(l.split(":", 1) for l in out.read_text().splitlines()
+                if ":" in l and not l.startswith("#"))
+    assert float(vals["fetch_scale"]) == pytest.approx(2.0)
+    assert float(vals["write_scale"]) == pytest.approx(1.0)
+    assert float(vals["fetch_bytes_per_launch"]) == pytest.approx(1.5 * 2**30)
+    assert float(vals["write_bytes_per_launch"]) == pytest.approx(2**30)
+    assert float(vals["traffic_over_algorithmic"]) == pytest.approx(1.25)
