@@ -341,3 +341,29 @@ def test_shutdown_stops_running_engines(ms):
     assert ms.ms_shutdown(e.ctx) == ms.MS_OK
     e.ctx = None
     assert time.time() - t0 < 5.0
+
+
+@pytest.mark.parametrize("rounds", [12, 8])
+def test_reduced_round_resident_kernels(ms, rounds):
+    """The engine dispatches the kernel of its context's round count."""
+    _note("resident rounds=%d" % rounds)
+    rng = np.random.default_rng(40 + rounds)
+    key_b = rng.bytes(32)
+    n = 37
+    data = workloads.random_pages(rng, n)
+    e = ms.Engine(0, rounds=rounds)
+    try:
+        buf = e.host_alloc(n * 4096)
+        buf.array[:] = data.reshape(-1)
+        r = e.resident(key=key_b, workers=32, idle_limit_ms=IDLE_MS)
+        try:
+            r.wait([r.submit(buf, buf, ms.linear_nonce(BASE, STRIDE, TAG))])
+        finally:
+            r.stop()
+        want = oracle.cipher_pages(
+            key_b, oracle.nonces_linear(n, BASE, STRIDE, TAG), data,
+            rounds=rounds)
+        assert np.array_equal(buf.array.reshape(n, 4096), want)
+        buf.free()
+    finally:
+        e.close()
