@@ -715,7 +715,9 @@ def main():
     ap.add_argument("--pages", type=int, default=262144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-pages", type=int, default=262144)
-    ap.add_argument("--cpu-reps", type=int, default=1)
+    ap.add_argument("--cpu-reps", type=int, default=25,
+                    help="passes of the CPU oracle (25 x 2 GiB is about "
+                         "10 s on 16 host threads)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-duration", type=float, default=10.0)
