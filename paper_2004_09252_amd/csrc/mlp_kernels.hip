@@ -156,19 +156,35 @@ __global__ void embed_gather_kernel(const uint16_t* __restrict__ E,
 
 // dE[v][d] = sum over (b, s) with ids[b][s] == v of dx[b][s*D + d], summed in
 // (b, s) order: one workgroup per vocabulary row, deterministic.
-__global__ void embed_scatter_kernel(const float* __restrict__ dx,
-                                     const int32_t* __restrict__ ids, int B,
-                                     int C, int D, int V,
-                                     float* __restrict__ dE) {
+// dE[v][d] = sum over positions i, in increasing order, with ids[i] == v of
+// dx[i][d].  One wave per embedding row: each step tests 64 positions at
+// once and the matching ones, found with a ballot, are added lowest first,
+// so the sum has a fixed order (deterministic) without scanning the
+// positions one at a time.
+__global__ __launch_bounds__(64) void embed_scatter_kernel(
+    const float* __restrict__ dx, const int32_t* __restrict__ ids, int B,
+    int C, int D, int V, float* __restrict__ dE) {
   const int v = blockIdx.x;
-  for (int d = threadIdx.x; d < D; d += blockDim.x) {
+  const int lane = threadIdx.x;
+  const int n = B * C;
+  for (int d0 = 0; d0 < D; d0 += 64) {
+    const int d = d0 + lane;
     float acc = 0.f;
-    for (int bs = 0; bs < B * C; ++bs) {
-      int id = ids[bs];
-      id = id < 0 ? 0 : (id >= V ? V - 1 : id);
-      if (id == v) acc += dx[(int64_t)bs * D + d];
+    for (int base = 0; base < n; base += 64) {
+      const int i = base + lane;
+      int id = -1;
+      if (i < n) {
+        id = ids[i];
+        id = id < 0 ? 0 : (id >= V ? V - 1 : id);
+      }
+      unsigned long long m = __ballot(id == v);
+      while (m) {
+        const int j = __ffsll(m) - 1;
+        m &= m - 1;
+        if (d < D) acc += dx[(int64_t)(base + j) * D + d];
+      }
     }
-    dE[(int64_t)v * D + d] = acc;
+    if (d < D) dE[(int64_t)v * D + d] = acc;
   }
 }
 
@@ -228,14 +244,27 @@ __global__ void mean_kernel(const float* __restrict__ v, int n,
   if (threadIdx.x == 0) *out = red[0] / (float)n;
 }
 
-// out[n] = sum over m of in[m][n] (float32), rows summed in order.
-__global__ void colsum_kernel(const float* __restrict__ in, int M, int N,
-                              int ld, float* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// out[n] = sum over m of in[m][n] (float32).  A workgroup takes 64 columns;
+// its 16 waves sum the rows g, g+16, g+32, ... of each column, and the 16
+// partial sums are added in a fixed tree order (deterministic).
+constexpr int kColsumGroups = 16;
+__global__ __launch_bounds__(64 * kColsumGroups) void colsum_kernel(
+    const float* __restrict__ in, int M, int N, int ld,
+    float* __restrict__ out) {
+  __shared__ float part[kColsumGroups][64];
+  const int c = threadIdx.x & 63;
+  const int g = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
   float s = 0.f;
-  for (int m = 0; m < M; ++m) s += in[(int64_t)m * ld + n];
-  out[n] = s;
+  if (n < N)
+    for (int m = g; m < M; m += kColsumGroups) s += in[(int64_t)m * ld + n];
+  part[g][c] = s;
+  __syncthreads();
+  for (int k = kColsumGroups / 2; k > 0; k >>= 1) {
+    if (g < k) part[g][c] += part[g + k][c];
+    __syncthreads();
+  }
+  if (g == 0 && n < N) out[n] = part[0][c];
 }
 
 __global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m,
@@ -452,7 +481,8 @@ ms_status ms_mlp_backward(const ms_mlp_shape* s, const uint16_t* P,
   GemmArgs g = gemm_args(w.h2, H, 1, w.dlH, V, 0, H, V, B);
   g.outF = G + off[5]; g.ldo = V;
   if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
-  hipLaunchKernelGGL(colsum_kernel, dim3((V + 255) / 256), dim3(256), 0, st,
+  hipLaunchKernelGGL(colsum_kernel, dim3((V + 63) / 64),
+                     dim3(64 * kColsumGroups), 0, st,
                      w.dlF, B, V, V, G + off[6]);
   g = gemm_args(w.dlH, V, 0, P + off[5], V, 1, B, H, V);
   g.mask = w.h2; g.ldm = H; g.outF = w.dz2F; g.ldo = H; g.outH = w.dz2H;
@@ -462,7 +492,8 @@ ms_status ms_mlp_backward(const ms_mlp_shape* s, const uint16_t* P,
   g = gemm_args(w.h1, H, 1, w.dz2H, H, 0, H, H, B);
   g.outF = G + off[3]; g.ldo = H;
   if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
-  hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256), dim3(256), 0, st,
+  hipLaunchKernelGGL(colsum_kernel, dim3((H + 63) / 64),
+                     dim3(64 * kColsumGroups), 0, st,
                      w.dz2F, B, H, H, G + off[4]);
   g = gemm_args(w.dz2H, H, 0, P + off[3], H, 1, B, H, H);
   g.mask = w.h1; g.ldm = H; g.outF = w.dz1F; g.ldo = H; g.outH = w.dz1H;
@@ -472,7 +503,8 @@ ms_status ms_mlp_backward(const ms_mlp_shape* s, const uint16_t* P,
   g = gemm_args(w.x, CD, 1, w.dz1H, H, 0, CD, H, B);
   g.outF = G + off[1]; g.ldo = H;
   if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
-  hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256), dim3(256), 0, st,
+  hipLaunchKernelGGL(colsum_kernel, dim3((H + 63) / 64),
+                     dim3(64 * kColsumGroups), 0, st,
                      w.dz1F, B, H, H, G + off[2]);
   g = gemm_args(w.dz1H, H, 0, P + off[1], H, 1, B, CD, H);
   g.outF = w.dxF; g.ldo = CD;
