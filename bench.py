@@ -506,8 +506,10 @@ def run_resident(args, ms, torch, b):
 
 def run_serving(args, ms, torch):
     """Poisson arrivals (20k req/s, 10 s, 1..256 pages log-uniform, 64 clients,
-    admission cap 8 GiB) through continuous batching and through one plain
-    launch per request; then a short rate sweep to compare GB/s at equal p99.
+    admission cap 8 GiB) through continuous batching, through one plain
+    launch per request, and through the resident-key ring (a kernel that
+    stays running with all 64 client keys on chip, one descriptor per page);
+    then a short rate sweep to compare GB/s at equal p99.
     Inputs are slices of a seeded 8 GiB device pool; every 100th request
     writes to its own slot and is checked against the oracle."""
     import numpy as np
@@ -530,7 +532,8 @@ def run_serving(args, ms, torch):
                                                lay.trace.n, pool_pages)}
     checked = 0
     for name, mode in (("served_batched", ms.MS_SERVE_BATCHED),
-                       ("plain_per_request", ms.MS_SERVE_PLAIN)):
+                       ("plain_per_request", ms.MS_SERVE_PLAIN),
+                       ("resident_ring", ms.MS_SERVE_RESIDENT)):
         log("serving %s" % name)
         dst.zero_()
         before = eng.stats()
@@ -565,7 +568,8 @@ def run_serving(args, ms, torch):
         ks = keys   # same 64 client keys
         row = {"rate_req_s": rate, "requests": int(ls.trace.n)}
         for name, mode in (("served", ms.MS_SERVE_BATCHED),
-                           ("plain", ms.MS_SERVE_PLAIN)):
+                           ("plain", ms.MS_SERVE_PLAIN),
+                           ("resident", ms.MS_SERVE_RESIDENT)):
             log("sweep %s %d req/s" % (name, rate))
             res, _ = serving.run(eng, ls, ks, src, dst, mode)
             row[name + "_GBps"] = round(res.data_gbps, 2)
@@ -577,7 +581,7 @@ def run_serving(args, ms, torch):
     table = []
     for bound in args.p99_bounds:
         row = {"p99_bound_us": bound}
-        for m in ("served", "plain"):
+        for m in ("served", "plain", "resident"):
             ok = [r[m + "_GBps"] for r in sweep if r[m + "_p99_us"] <= bound]
             row[m + "_GBps"] = max(ok) if ok else None
         table.append(row)

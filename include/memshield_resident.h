@@ -18,10 +18,17 @@
  *     each) into a ring in pinned host memory; any number of host threads may
  *     submit; the kernel's workers take descriptors in ring order;
  *   - pages are in pinned, coherent host memory (ms_host_alloc of
- *     memshield_host.h, or hipHostMalloc with hipHostMallocCoherent): the
- *     kernel reads and writes them while it runs; nonces follow
- *     the linear rule (virtual address, PID) of ms_nonce, which is the
- *     paper's;
+ *     memshield_host.h, or hipHostMalloc with hipHostMallocCoherent), which
+ *     is the paper's data path, or in device memory of the context's GPU
+ *     (a page request then never waits for a kernel launch); the kernel
+ *     reads and writes them while it runs; nonces follow the linear rule
+ *     (virtual address, PID) of ms_nonce, which is the paper's;
+ *   - an engine holds one key (the paper's design: it stays in every
+ *     worker's registers) or, started with ms_resident_start_keys, up to
+ *     MS_RESIDENT_MAX_KEYS keys taken from the context's key table (one per
+ *     client, say), which each workgroup of the kernel keeps in its LDS; a
+ *     descriptor names its key by index.  Either way the keys are wiped from
+ *     device memory once every worker holds them and live on chip only;
  *   - completion is a word per ring slot written by the kernel into host
  *     memory and read by ms_resident_poll, with no GPU call on the way.
  * The cipher is the same as ms_encrypt_pages with the same key: output bytes
@@ -46,6 +53,8 @@ extern "C" {
 #endif
 
 typedef struct ms_resident ms_resident;  /* opaque */
+
+#define MS_RESIDENT_MAX_KEYS 64
 
 typedef struct ms_resident_config {
     uint32_t workers;        /* worker waves (default 256; at most 4 per
@@ -73,18 +82,41 @@ ms_status ms_resident_start(ms_ctx *ctx, const ms_resident_config *cfg,
                             const uint8_t *key, ms_resident **out);
 
 /*
- * Queue n_pages pages from src to dst (pinned host memory, 16-byte aligned,
- * src == dst or not overlapping) with a linear nonce.  The request becomes
- * ceil(n_pages / desc_pages) descriptors, queued together or not at all; the
- * ticket covers all of them.  Never blocks.  Errors: MS_EINVAL (including
- * device memory, pageable memory or more descriptors than the ring holds),
- * MS_ENOTSUP (array nonces), MS_EAGAIN (ring full now), MS_ECLOSED (the
- * kernel has stopped), MS_EDEVICE (the kernel rejected a descriptor).
- * Thread-safe.
+ * Start an engine that holds n_keys (1..MS_RESIDENT_MAX_KEYS) keys of the
+ * context's key table: keys[i] becomes key index i of ms_resident_submit_keyed.
+ * The key bytes are copied device to device (never through host memory);
+ * the handles stay valid and usable on the context, and destroying one later
+ * does not reach the engine's copy.  Errors as ms_resident_start, plus
+ * MS_ENOKEY for an unknown handle.
+ */
+ms_status ms_resident_start_keys(ms_ctx *ctx, const ms_resident_config *cfg,
+                                 const ms_key *keys, uint32_t n_keys,
+                                 ms_resident **out);
+
+/*
+ * Queue n_pages pages from src to dst with key index 0 and a linear nonce;
+ * ms_resident_submit_keyed with key_index 0.
  */
 ms_status ms_resident_submit(ms_resident *r, const void *src, void *dst,
                              uint64_t n_pages, const ms_nonce *nonce,
                              ms_ticket *ticket_out);
+
+/*
+ * Queue n_pages pages from src to dst with the engine's key `key_index` and
+ * a linear nonce.  src and dst are each pinned host memory or device memory
+ * of the context's GPU, 16-byte aligned, src == dst or not overlapping.  The
+ * request becomes ceil(n_pages / desc_pages) descriptors, queued together or
+ * not at all; the ticket covers all of them.  Never blocks.  Errors:
+ * MS_EINVAL (a key index the engine does not hold, pageable or managed
+ * memory, another GPU's memory, or more descriptors than the ring holds),
+ * MS_ENOTSUP (array nonces), MS_EAGAIN (ring full now), MS_ECLOSED (the
+ * kernel has stopped), MS_EDEVICE (the kernel rejected a descriptor).
+ * Thread-safe.
+ */
+ms_status ms_resident_submit_keyed(ms_resident *r, uint32_t key_index,
+                                   const void *src, void *dst,
+                                   uint64_t n_pages, const ms_nonce *nonce,
+                                   ms_ticket *ticket_out);
 
 /*
  * done_out[i] = 1 when ticket i's pages are written, 0 while pending, or
@@ -109,8 +141,8 @@ ms_status ms_resident_stop(ms_resident *r);
 
 /*
  * Test hook for the key-purge property: 1 when both the device key buffer
- * and the host staging buffer hold only zero bytes, 0 otherwise, negative on
- * error.
+ * (all the engine's keys) and the host staging buffer hold only zero bytes,
+ * 0 otherwise, negative on error.
  */
 int ms_resident_debug_key_wiped(ms_resident *r);
 

@@ -12,7 +12,15 @@
  *   MS_SERVE_PLAIN - one dispatcher thread issues each request at its arrival
  *     as its own plain launch (ms_encrypt_pages) on one stream, records an
  *     event after it, and a poller observes the events in order: the
- *     one-launch-per-request baseline.
+ *     one-launch-per-request baseline;
+ *   MS_SERVE_RESIDENT - no launch per request: the run starts a resident-key
+ *     engine (memshield_resident.h) holding every client's key (copied from
+ *     the context's key table; at most MS_RESIDENT_MAX_KEYS clients), with
+ *     one descriptor per page and 4 * compute units - 1 workers; client
+ *     threads submit each request into its ring at arrival, a poller
+ *     observes completion words in host memory, and the engine is stopped
+ *     at the end.  This is the paper's own serving design (a kernel that
+ *     never ends, fed through a ring in mapped memory) on device pages.
  * The paper's server handles many clients' page requests concurrently
  * through per-worker multiple-producer queues (section 4.4); this harness
  * drives the engine's equivalent with synthetic traffic.
@@ -26,7 +34,11 @@
 extern "C" {
 #endif
 
-typedef enum ms_serve_mode { MS_SERVE_BATCHED = 0, MS_SERVE_PLAIN = 1 } ms_serve_mode;
+typedef enum ms_serve_mode {
+    MS_SERVE_BATCHED = 0,
+    MS_SERVE_PLAIN = 1,
+    MS_SERVE_RESIDENT = 2
+} ms_serve_mode;
 
 /* Host arrays of n entries each (request i). */
 typedef struct ms_serve_trace {
@@ -57,7 +69,7 @@ typedef struct ms_serve_result {
  * src_pool_pages / dst_pool_pages pages; every request must fit inside them
  * (MS_EINVAL otherwise, checked before anything runs).  keys[client] is the
  * key of each client.  submit_threads client threads share the arrivals in
- * batched mode (1..64).  latency_us_out (may be NULL) receives n latencies,
+ * batched and resident modes (1..64).  latency_us_out (may be NULL) receives n latencies,
  * arrival to observed completion.  Pages a request writes must not be read
  * or written by any request still in flight (the caller lays out dst).
  * Errors: MS_EINVAL, MS_EDEVICE, MS_ETIMEDOUT (a request did not complete

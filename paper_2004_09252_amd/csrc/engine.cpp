@@ -1370,3 +1370,18 @@ ms_status ms_internal_launch_plain(ms_ctx* c, uint32_t key_slot,
                           max_waves);
 }
 HostPath* ms_internal_host_path(ms_ctx* c) { return c->host; }
+ms_status ms_internal_copy_key(ms_ctx* c, ms_key key, void* dst,
+                               hipStream_t stream) {
+  // the handle check of resolve_key, made under the lock held for the copy
+  // (resolve_key takes the same lock itself)
+  const uint32_t s = (uint32_t)(key & 0xffffffffu);
+  const uint32_t g = (uint32_t)(key >> 32);
+  if (key == 0 || s == 0 || s > c->cfg.max_keys) return MS_ENOKEY;
+  std::lock_guard<std::mutex> lk(c->key_mu);
+  if (!c->key_live[s - 1] || c->key_gen[s - 1] != g) return MS_ENOKEY;
+  const uint32_t slot = s - 1;
+  hipError_t e = hipMemcpyAsync(dst, c->d_keys + (size_t)slot * 8,
+                                MS_KEY_BYTES, hipMemcpyDeviceToDevice, stream);
+  if (hip_ok(e)) e = hipStreamSynchronize(stream);
+  return hip_ok(e) ? MS_OK : dev_err(c, e);
+}

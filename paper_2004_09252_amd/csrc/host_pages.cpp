@@ -293,6 +293,15 @@ ms_status ms_internal_classify_host(ms_ctx* c, const void* p, uint64_t bytes,
   return MS_OK;
 }
 
+ms_status ms_internal_classify_any(ms_ctx* c, const void* p, uint64_t bytes,
+                                   uint64_t align, uint64_t* gpu) {
+  Buf b{};
+  ms_status st = classify(c, p, bytes, align, &b);
+  if (st) return st;
+  *gpu = reinterpret_cast<uint64_t>(b.gpu);
+  return MS_OK;
+}
+
 HostPath* ms_internal_host_path_create() {
   return new (std::nothrow) HostPath();
 }

@@ -43,6 +43,16 @@ HostPath* ms_internal_host_path(ms_ctx* c);
 // the address the GPU uses for p.  MS_EINVAL for anything else.
 ms_status ms_internal_classify_host(ms_ctx* c, const void* p, uint64_t bytes,
                                     uint64_t align, uint64_t* gpu);
+// The same, but [p, p+bytes) may also be device memory of the context's GPU
+// (then *gpu = p).
+ms_status ms_internal_classify_any(ms_ctx* c, const void* p, uint64_t bytes,
+                                   uint64_t align, uint64_t* gpu);
+
+// Copies the 32 key bytes of `key` from the key table into device memory at
+// `dst` (device to device, on `stream`, waited for), under the key lock so
+// the key cannot be destroyed meanwhile.  MS_ENOKEY for an unknown handle.
+ms_status ms_internal_copy_key(ms_ctx* c, ms_key key, void* dst,
+                               hipStream_t stream);
 
 // Stops every resident-key engine of the context (resident.cpp).
 void ms_internal_resident_stop_all(ms_ctx* c);

@@ -7,9 +7,13 @@
 
 namespace ms {
 
+// Most keys one engine holds; its table lives in each workgroup's LDS.
+constexpr uint32_t kRkMaxKeys = 64;
+
 // One descriptor of the host's submission ring: a run of pages (at most
-// max_pages) in GPU-visible host memory, ciphered with the resident key and
-// the linear nonce rule.  64 bytes, in pinned host memory.
+// max_pages) in pinned host memory or device memory, ciphered with one of
+// the resident keys and the linear nonce rule.  64 bytes, in pinned host
+// memory.
 struct RkDesc {
   uint64_t src;           // GPU-visible address of the first source page
   uint64_t dst;           // same for the destination
@@ -18,7 +22,9 @@ struct RkDesc {
   uint64_t seq;           // ring position the descriptor was written for
   uint32_t n_pages;
   uint32_t tag;           // state word 15
-  uint64_t pad[2];
+  uint32_t key;           // index into the engine's keys, < n_keys
+  uint32_t pad32;
+  uint64_t pad;
 };
 static_assert(sizeof(RkDesc) == 64, "RkDesc layout");
 
@@ -51,18 +57,20 @@ struct RkArgs {
                           // descriptor finished in it
   RkHostCtl* hctl;
   RkDevCtl* dctl;
-  uint32_t* key_buf;      // device, 8 words; wiped once every worker has them
+  uint32_t* key_buf;      // device, n_keys x 8 words; wiped once every
+                          // worker holds them (registers, or LDS tables)
   uint64_t idle_ticks;    // 100 MHz ticks without host activity before the
                           // kernel ends itself; 0 = no limit
   uint32_t ring_mask;
   uint32_t n_workers;     // worker waves (the poller is one more wave)
   uint32_t max_pages;     // pages per descriptor
-  uint32_t pad;
+  uint32_t n_keys;        // 1: the key stays in every worker's registers;
+                          // 2..kRkMaxKeys: a table in each workgroup's LDS
 };
 
 // Kernel entry points (plain C names in the separately built code object),
 // one per round count; launched as (n_workers + 1) waves in 256-thread
-// workgroups with 16 KiB of LDS per workgroup.
+// workgroups (the group segment size comes from the code object).
 constexpr const char* kResidentKernel20 = "ms_resident_pages_r20.kd";
 constexpr const char* kResidentKernel12 = "ms_resident_pages_r12.kd";
 constexpr const char* kResidentKernel8 = "ms_resident_pages_r8.kd";

@@ -39,6 +39,8 @@
 #include "ms_kernels.h"
 #include "ms_resident_kernel.h"
 
+static_assert(ms::kRkMaxKeys == MS_RESIDENT_MAX_KEYS, "key table size");
+
 extern "C" const unsigned char ms_resident_code_object[];
 extern "C" const size_t ms_resident_code_object_size;
 
@@ -63,7 +65,8 @@ struct ms_resident {
   uint64_t* completed = nullptr;  // pinned, ring_depth words
   uint8_t* staging = nullptr;     // pinned, 32 bytes
   ms::RkDevCtl* dctl = nullptr;   // device
-  uint32_t* key_buf = nullptr;    // device, 8 words
+  uint32_t* key_buf = nullptr;    // device, n_keys x 8 words
+  uint32_t n_keys = 1;
   bool launched = false;
   std::mutex mu;                  // producers
   uint64_t next_pos = 0;
@@ -126,7 +129,9 @@ bool release(ms_resident* r) {
   if (r->hsa_up) (void)hsa_shut_down();
   if (r->kernarg) (void)hipHostFree(r->kernarg);
   if (r->key_buf) {
-    if (r->aux && hip_ok(hipMemsetAsync(r->key_buf, 0, 32, r->aux)))
+    if (r->aux && hip_ok(hipMemsetAsync(r->key_buf, 0,
+                                        (size_t)r->n_keys * MS_KEY_BYTES,
+                                        r->aux)))
       (void)hipStreamSynchronize(r->aux);
     (void)hipFree(r->key_buf);
   }
@@ -310,9 +315,17 @@ void ms_resident_config_default(ms_resident_config* cfg) {
   cfg->idle_limit_ms = 10000;
 }
 
-ms_status ms_resident_start(ms_ctx* c, const ms_resident_config* cfg_in,
-                            const uint8_t* key, ms_resident** out) {
-  if (!c || !out) return MS_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Start an engine with n_keys keys: from `key_bytes` (32 bytes, n_keys == 1),
+// from the OS CSPRNG (both null, n_keys == 1), or copied device to device
+// from the context's key table (`handles`).
+ms_status start_engine(ms_ctx* c, const ms_resident_config* cfg_in,
+                       const uint8_t* key_bytes, const ms_key* handles,
+                       uint32_t n_keys, ms_resident** out) {
+  if (!c || !out || n_keys == 0 || n_keys > ms::kRkMaxKeys) return MS_EINVAL;
   ms_status st = ms_internal_sticky(c);
   if (st) return st;
   ms_resident_config cfg;
@@ -341,7 +354,9 @@ ms_status ms_resident_start(ms_ctx* c, const ms_resident_config* cfg_in,
   r->device = ms_internal_device(c);
   r->cfg = cfg;
   r->workers = cfg.workers;
+  r->n_keys = n_keys;
   const size_t depth = cfg.ring_depth;
+  const size_t key_bytes_total = (size_t)n_keys * MS_KEY_BYTES;
   bool ok = hip_ok(hipStreamCreateWithFlags(&r->aux, hipStreamNonBlocking));
   if (!ok) {
     (void)hipGetLastError();
@@ -361,39 +376,56 @@ ms_status ms_resident_start(ms_ctx* c, const ms_resident_config* cfg_in,
                             MS_KEY_BYTES, hipHostMallocDefault)) &&
        hip_ok(hipMalloc(reinterpret_cast<void**>(&r->dctl),
                         sizeof(ms::RkDevCtl))) &&
-       hip_ok(hipMalloc(reinterpret_cast<void**>(&r->key_buf), MS_KEY_BYTES));
+       hip_ok(hipMalloc(reinterpret_cast<void**>(&r->key_buf),
+                        key_bytes_total));
   if (!ok) {
     (void)hipGetLastError();
     release(r);
     return MS_ENOMEM;
   }
   std::memset(r->hctl, 0, sizeof(ms::RkHostCtl));
+  std::memset(r->staging, 0, MS_KEY_BYTES);
   std::memset(r->ring, 0, depth * sizeof(ms::RkDesc));
   std::memset(r->completed, 0, depth * sizeof(uint64_t));
-  // key: caller's bytes or the OS CSPRNG, into pinned staging, to the GPU,
-  // then wiped from the staging buffer
-  if (key) {
-    std::memcpy(r->staging, key, MS_KEY_BYTES);
-  } else {
-    size_t got = 0;
-    while (got < MS_KEY_BYTES) {
-      const ssize_t n = getrandom(r->staging + got, MS_KEY_BYTES - got, 0);
-      if (n < 0) {
-        release(r);
-        return MS_EDEVICE;
-      }
-      got += (size_t)n;
-    }
-  }
   hipError_t e = hipMemsetAsync(r->dctl, 0, sizeof(ms::RkDevCtl), r->aux);
-  if (hip_ok(e))
-    e = hipMemcpyAsync(r->key_buf, r->staging, MS_KEY_BYTES,
-                       hipMemcpyHostToDevice, r->aux);
-  if (hip_ok(e)) e = hipStreamSynchronize(r->aux);
-  wipe(r->staging, MS_KEY_BYTES);
   if (!hip_ok(e)) {
     release(r);
     return ms_internal_dev_err(c, e);
+  }
+  if (handles) {
+    // keys already on the device: copied from the context's key table, never
+    // through host memory
+    for (uint32_t i = 0; i < n_keys && !st; ++i)
+      st = ms_internal_copy_key(c, handles[i], r->key_buf + (size_t)i * 8,
+                                r->aux);
+    if (st) {
+      release(r);
+      return st;
+    }
+  } else {
+    // key: caller's bytes or the OS CSPRNG, into pinned staging, to the GPU,
+    // then wiped from the staging buffer
+    if (key_bytes) {
+      std::memcpy(r->staging, key_bytes, MS_KEY_BYTES);
+    } else {
+      size_t got = 0;
+      while (got < MS_KEY_BYTES) {
+        const ssize_t n = getrandom(r->staging + got, MS_KEY_BYTES - got, 0);
+        if (n < 0) {
+          release(r);
+          return MS_EDEVICE;
+        }
+        got += (size_t)n;
+      }
+    }
+    e = hipMemcpyAsync(r->key_buf, r->staging, MS_KEY_BYTES,
+                       hipMemcpyHostToDevice, r->aux);
+    if (hip_ok(e)) e = hipStreamSynchronize(r->aux);
+    wipe(r->staging, MS_KEY_BYTES);
+    if (!hip_ok(e)) {
+      release(r);
+      return ms_internal_dev_err(c, e);
+    }
   }
   ms::RkArgs a{};
   a.ring = r->ring;
@@ -405,12 +437,13 @@ ms_status ms_resident_start(ms_ctx* c, const ms_resident_config* cfg_in,
   a.ring_mask = cfg.ring_depth - 1;
   a.n_workers = r->workers;
   a.max_pages = cfg.desc_pages;
+  a.n_keys = n_keys;
   st = dispatch(r, a, rounds);
   if (st) {
     release(r);
     return st;
   }
-  // wait for every worker to hold the key (the kernel then wipes its copy)
+  // wait for every worker to hold the keys (the kernel then wipes its copy)
   const auto deadline = Clock::now() + std::chrono::seconds(10);
   while (!load_acq(&r->hctl->ready)) {
     if (kernel_exited(r) || Clock::now() > deadline) {
@@ -427,18 +460,42 @@ ms_status ms_resident_start(ms_ctx* c, const ms_resident_config* cfg_in,
   return MS_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+ms_status ms_resident_start(ms_ctx* c, const ms_resident_config* cfg,
+                            const uint8_t* key, ms_resident** out) {
+  return start_engine(c, cfg, key, nullptr, 1, out);
+}
+
+ms_status ms_resident_start_keys(ms_ctx* c, const ms_resident_config* cfg,
+                                 const ms_key* keys, uint32_t n_keys,
+                                 ms_resident** out) {
+  if (!keys) return MS_EINVAL;
+  return start_engine(c, cfg, nullptr, keys, n_keys, out);
+}
+
 ms_status ms_resident_submit(ms_resident* r, const void* src, void* dst,
                              uint64_t n_pages, const ms_nonce* nonce,
                              ms_ticket* ticket_out) {
-  if (!r || !nonce || n_pages == 0) return MS_EINVAL;
+  return ms_resident_submit_keyed(r, 0, src, dst, n_pages, nonce, ticket_out);
+}
+
+ms_status ms_resident_submit_keyed(ms_resident* r, uint32_t key_index,
+                                   const void* src, void* dst,
+                                   uint64_t n_pages, const ms_nonce* nonce,
+                                   ms_ticket* ticket_out) {
+  if (!r || !nonce || n_pages == 0 || key_index >= r->n_keys)
+    return MS_EINVAL;
   if (nonce->kind == MS_NONCE_ARRAY) return MS_ENOTSUP;
   if (nonce->kind != MS_NONCE_LINEAR) return MS_EINVAL;
   if (n_pages > UINT64_MAX / MS_PAGE_SIZE) return MS_EINVAL;
   const uint64_t bytes = n_pages * MS_PAGE_SIZE;
   uint64_t s = 0, d = 0;
-  ms_status st = ms_internal_classify_host(r->ctx, src, bytes, 16, &s);
+  ms_status st = ms_internal_classify_any(r->ctx, src, bytes, 16, &s);
   if (st) return st;
-  if ((st = ms_internal_classify_host(r->ctx, dst, bytes, 16, &d))) return st;
+  if ((st = ms_internal_classify_any(r->ctx, dst, bytes, 16, &d))) return st;
   const uintptr_t a = reinterpret_cast<uintptr_t>(src);
   const uintptr_t b = reinterpret_cast<uintptr_t>(dst);
   if (a != b && a < b + bytes && b < a + bytes) return MS_EINVAL;
@@ -464,6 +521,7 @@ ms_status ms_resident_submit(ms_resident* r, const void* src, void* dst,
     x.nonce_stride = nonce->stride;
     x.n_pages = (uint32_t)(n_pages - first < per ? n_pages - first : per);
     x.tag = nonce->tag;
+    x.key = key_index;
     x.seq = q;
   }
   store_rel(&r->hctl->published, p0 + m);
@@ -531,8 +589,9 @@ ms_status ms_resident_stop(ms_resident* r) {
 
 int ms_resident_debug_key_wiped(ms_resident* r) {
   if (!r) return -1;
-  uint32_t dev[8] = {1, 1, 1, 1, 1, 1, 1, 1};
-  if (!hip_ok(hipMemcpyAsync(dev, r->key_buf, MS_KEY_BYTES,
+  std::vector<uint32_t> dev((size_t)r->n_keys * 8, 1u);
+  if (!hip_ok(hipMemcpyAsync(dev.data(), r->key_buf,
+                             (size_t)r->n_keys * MS_KEY_BYTES,
                              hipMemcpyDeviceToHost, r->aux)) ||
       !hip_ok(hipStreamSynchronize(r->aux)))
     return -1;

@@ -14,13 +14,20 @@
 //     counts itself in, and the last worker zeroes the buffer and tells the
 //     host; from then on the key exists only in registers (no scratch: the
 //     kernel's resource usage is checked to be spill-free);
-//   * the host writes 64-byte descriptors (a run of host pages, its linear
-//     nonce) into a ring in pinned host memory and publishes a count; the
+//   * an engine may instead hold up to kRkMaxKeys keys (one per client, say):
+//     each workgroup copies them into a table in its LDS before its waves
+//     start, the last worker wipes the device buffer as above, and a worker
+//     moves the key its descriptor names from LDS into SGPRs; the keys then
+//     live only on chip (LDS and registers), never in HBM or host memory;
+//   * the host writes 64-byte descriptors (a run of pages in pinned host
+//     memory or in device memory, its linear nonce, its key index) into a
+//     ring in pinned host memory and publishes a count; the
 //     poller wave reads that count over the link and mirrors it into device
 //     memory, so the idle workers, each holding a claimed ring position,
 //     wait on device memory instead of polling across the link;
 //   * a worker reads its descriptor and the pages with system-scope loads
-//     (coalesced 8-byte columns, no stale cached copy is possible), XORs the
+//     (coalesced 8-byte columns, no stale cached copy is possible, whether a
+//     page is in host memory or in HBM), XORs the
 //     keystream, transposed through LDS as in the launch-per-call kernels,
 //     writes the pages back with system-scope stores, and after a release
 //     fence writes the position into the slot's completion word, which the
@@ -35,6 +42,7 @@
 //     a loop back-edge can otherwise be compiled into an exec-mask loop that
 //     some lanes leave and others do not.
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "cipher_core.h"
@@ -107,24 +115,51 @@ __device__ void poll_host(const RkArgs& a, uint32_t lane) {
 }
 
 // Cipher the pages of the descriptor at ring position `pos`, then mark the
-// position complete.  A descriptor that does not carry its own position, or
-// has a page count outside 1..max_pages, is not touched and raises `error`.
+// position complete.  A descriptor that does not carry its own position, has
+// a page count outside 1..max_pages or a key index outside the engine's keys
+// is not touched and raises `error`.  `k` is the key of a one-key engine;
+// `keytab` the LDS key table of a many-key engine.
 template <int ROUNDS>
 __device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
-                          uint64_t pos, uint4* lds, uint32_t lane) {
-  const RkDesc* d = a.ring + (pos & a.ring_mask);
-  const uint64_t seq = uni64(ld_sys64(&d->seq));
-  const uint64_t src = uni64(ld_sys64(&d->src));
-  const uint64_t dst = uni64(ld_sys64(&d->dst));
-  const uint64_t nb = uni64(ld_sys64(&d->nonce_base));
-  const uint64_t ns = uni64(ld_sys64(&d->nonce_stride));
-  const uint64_t pt = uni64(ld_sys64(reinterpret_cast<const uint64_t*>(
-      &d->n_pages)));  // n_pages | tag << 32
+                          const uint32_t* keytab, uint64_t pos, uint4* lds,
+                          uint32_t lane) {
+  // the descriptor in one 64-byte read: lane l loads its word l % 8 (the
+  // lanes past 7 repeat those addresses, which the wave's load merges), and
+  // each field is taken from the lane that holds it
+  const uint64_t wv = ld_sys64(reinterpret_cast<const uint64_t*>(
+                                   a.ring + (pos & a.ring_mask)) +
+                               (lane & 7u));
+  const uint32_t wlo = (uint32_t)wv, whi = (uint32_t)(wv >> 32);
+  auto field = [&](int i) -> uint64_t {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)whi, i) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)wlo, i);
+  };
+  static_assert(offsetof(RkDesc, seq) == 32 && offsetof(RkDesc, n_pages) == 40 &&
+                    offsetof(RkDesc, key) == 48,
+                "descriptor words");
+  const uint64_t src = field(0);
+  const uint64_t dst = field(1);
+  const uint64_t nb = field(2);
+  const uint64_t ns = field(3);
+  const uint64_t seq = field(4);
+  const uint64_t pt = field(5);  // n_pages | tag << 32
+  const uint32_t key = (uint32_t)field(6);
   const uint32_t n_pages = (uint32_t)pt;
   const uint32_t tag = (uint32_t)(pt >> 32);
-  if (seq != pos || n_pages == 0 || n_pages > a.max_pages) {
+  if (seq != pos || n_pages == 0 || n_pages > a.max_pages ||
+      key >= a.n_keys) {
     st_sys32(&a.hctl->error, 1u);
   } else {
+    uint32_t kk[8];
+    if (a.n_keys > 1) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) kk[i] = uni(keytab[key * 8u + i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) kk[i] = k[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) asm volatile("" : "+s"(kk[i]) : : "memory");
     for (uint32_t p = 0; p < n_pages; ++p) {
       const uint64_t s = src + (uint64_t)p * kPageBytes;
       const uint64_t o = dst + (uint64_t)p * kPageBytes;
@@ -136,7 +171,7 @@ __device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
       const uint64_t nv = nb + (uint64_t)p * ns;
       const uint32_t n[3] = {(uint32_t)nv, (uint32_t)(nv >> 32), tag};
       uint32_t ks[16];
-      keystream<ROUNDS>(ks, k, n, lane);  // block `lane` = bytes 64*lane..
+      keystream<ROUNDS>(ks, kk, n, lane);  // block `lane` = bytes 64*lane..
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         lds[lds_slot(lane * 4 + q)] =
@@ -152,16 +187,29 @@ __device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
       wave_lds_order();
     }
   }
-  // the page stores reach the host before the completion word does
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+  // The page stores are complete before the completion word is written.
+  // Every global store of this worker since its last completion word is a
+  // system-scope store, which the L2 writes through instead of holding
+  // dirty, so waiting for those stores to be acknowledged orders them before
+  // the completion store (the asm's memory clobber keeps the compiler from
+  // moving either across it).  A release fence would add a write-back of
+  // the whole L2, which serializes across the device: with one descriptor
+  // per page, a 256-page request took 33 us that way against 13 us so.
+  asm volatile("s_waitcnt vmcnt(0)" : : : "memory");
   st_sys64(&a.completed[pos & a.ring_mask], pos + 1);
 }
 
 template <int ROUNDS>
-__device__ void serve_ring(const RkArgs& a, uint4* lds, uint32_t lane) {
+__device__ void serve_ring(const RkArgs& a, const uint32_t* keytab,
+                           uint4* lds, uint32_t lane) {
   uint32_t k[8];
+  if (a.n_keys == 1) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) k[i] = uni(ld_sys32(a.key_buf + i));
+    for (int i = 0; i < 8; ++i) k[i] = uni(ld_sys32(a.key_buf + i));
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) k[i] = 0;  // keys come from `keytab`
+  }
 #pragma unroll
   for (int i = 0; i < 8; ++i) asm volatile("" : "+s"(k[i]) : : "memory");
   // one count per wave: lane 0 adds 1, the other lanes 0; lane 0's result
@@ -170,8 +218,11 @@ __device__ void serve_ring(const RkArgs& a, uint4* lds, uint32_t lane) {
       &a.dctl->key_loads, lane == 0 ? 1u : 0u, __ATOMIC_ACQ_REL,
       __HIP_MEMORY_SCOPE_AGENT));
   if (before + 1 == a.n_workers) {
-    // every worker now holds the key in registers: wipe the memory copy
-    st_sys32(a.key_buf + (lane & 7u), 0u);
+    // every worker now holds the keys (registers, or its workgroup's LDS
+    // table): wipe the memory copy; lanes past the end repeat the last word
+    const uint32_t words = a.n_keys * 8u;
+    for (uint32_t i = 0; i < words; i += kWave)
+      st_sys32(a.key_buf + min(i + lane, words - 1), 0u);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
     st_sys32(&a.hctl->ready, 1u);
   }
@@ -181,32 +232,47 @@ __device__ void serve_ring(const RkArgs& a, uint4* lds, uint32_t lane) {
         &a.dctl->claimed, lane == 0 ? (uint64_t)1 : (uint64_t)0,
         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     // wait on device memory until the position is published, or stop; the
-    // worker holding the next position to be published polls fastest
+    // worker holding the next position to be published polls fastest, the
+    // next 63 (the rest of a request of up to 64 descriptors) every ~500
+    // cycles, the others every ~4000, which keeps the load on the word low
     for (;;) {
       const uint64_t pub = uni64(ld_dev64(&a.dctl->published));
       if (pos < pub) break;
       if (uni(ld_dev32(&a.dctl->stop))) return;
       if (pos == pub)
         __builtin_amdgcn_s_sleep(2);
+      else if (pos - pub < 64)
+        __builtin_amdgcn_s_sleep(8);
       else
         __builtin_amdgcn_s_sleep(64);
     }
-    serve_one<ROUNDS>(a, k, pos, lds, lane);
+    serve_one<ROUNDS>(a, k, keytab, pos, lds, lane);
   }
 }
 
 template <int ROUNDS>
 __device__ __forceinline__ void resident_pages(const RkArgs& a) {
   __shared__ uint4 lds[kWavesPerBlock][256];
+  __shared__ uint32_t keytab[kRkMaxKeys * 8];
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t w = wave_in_block();
   const uint32_t gw = blockIdx.x * kWavesPerBlock + w;
+  if (a.n_keys > 1) {
+    // many keys: the whole workgroup copies the table into LDS; threads past
+    // the end repeat the last word
+    const uint32_t words = a.n_keys * 8u;
+    for (uint32_t i = 0; i < words; i += kBlockThreads) {
+      const uint32_t j = min(i + threadIdx.x, words - 1);
+      keytab[j] = ld_sys32(a.key_buf + j);
+    }
+  }
+  __syncthreads();
   if (gw == 0) {
     poll_host(a, lane);
     return;
   }
   if (gw > a.n_workers) return;
-  serve_ring<ROUNDS>(a, lds[w], lane);
+  serve_ring<ROUNDS>(a, keytab, lds[w], lane);
 }
 
 }  // namespace

@@ -10,7 +10,9 @@
 #include <vector>
 
 #include "memshield.h"
+#include "memshield_resident.h"
 #include "memshield_serve.h"
+#include "ms_internal.h"
 
 namespace {
 
@@ -67,7 +69,11 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
                                   int32_t mode, uint32_t submit_threads,
                                   double* lat_out, ms_serve_result* res) {
   if (!c || !tr || !keys || !res || !src_pool || !dst_pool) return MS_EINVAL;
-  if (mode != MS_SERVE_BATCHED && mode != MS_SERVE_PLAIN) return MS_EINVAL;
+  if (mode != MS_SERVE_BATCHED && mode != MS_SERVE_PLAIN &&
+      mode != MS_SERVE_RESIDENT)
+    return MS_EINVAL;
+  if (mode == MS_SERVE_RESIDENT && n_keys > MS_RESIDENT_MAX_KEYS)
+    return MS_EINVAL;
   if (submit_threads == 0 || submit_threads > 64) return MS_EINVAL;
   const uint64_t n = tr->n;
   for (uint64_t i = 0; i < n; ++i) {
@@ -81,6 +87,20 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
   std::memset(res, 0, sizeof(*res));
   if (n == 0) return MS_OK;
 
+  // resident mode: one engine holding every client's key, one descriptor per
+  // page (so a request's pages are ciphered by as many waves at once), as
+  // many workers as one workgroup per compute unit allows
+  ms_resident* rk = nullptr;
+  if (mode == MS_SERVE_RESIDENT) {
+    ms_resident_config rc;
+    ms_resident_config_default(&rc);
+    rc.workers = (uint32_t)ms_internal_cu_count(c) * 4u - 1u;
+    rc.desc_pages = 1;
+    rc.ring_depth = 1u << 16;
+    const ms_status rs = ms_resident_start_keys(c, &rc, keys, n_keys, &rk);
+    if (rs != MS_OK) return rs;
+  }
+
   std::vector<Clock::time_point> done_t(n);
   std::vector<double> late(n, 0.0);
   std::vector<int32_t> state(n, 0);
@@ -93,7 +113,16 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
   };
   ms_status st = MS_OK;
 
-  if (mode == MS_SERVE_BATCHED) {
+  if (mode == MS_SERVE_BATCHED || mode == MS_SERVE_RESIDENT) {
+    auto submit_one = [&](uint64_t i, const ms_request& r, ms_ticket* tk) {
+      if (rk)
+        return ms_resident_submit_keyed(rk, tr->client[i], r.src, r.dst,
+                                        r.n_pages, &r.nonce, tk);
+      return ms_submit(c, &r, 1, tk);
+    };
+    auto poll_some = [&](const ms_ticket* t, size_t m, int32_t* dn) {
+      return rk ? ms_resident_poll(rk, t, m, dn, 0) : ms_poll(c, t, m, dn, 0);
+    };
     std::mutex mu;
     std::vector<std::pair<uint64_t, ms_ticket>> fresh;
     std::atomic<uint32_t> submitters_done{0};
@@ -104,7 +133,7 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
         ms_request r = make_request(tr, i, keys, src_pool, dst_pool);
         ms_ticket tk = 0;
         for (;;) {
-          const ms_status s = ms_submit(c, &r, 1, &tk);
+          const ms_status s = submit_one(i, r, &tk);
           if (s == MS_OK) break;
           if (s != MS_EAGAIN) {
             fail.store(s);
@@ -141,7 +170,7 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
       tks.resize(pend.size());
       dn.resize(pend.size());
       for (size_t k = 0; k < pend.size(); ++k) tks[k] = pend[k].second;
-      const ms_status ps = ms_poll(c, tks.data(), tks.size(), dn.data(), 0);
+      const ms_status ps = poll_some(tks.data(), tks.size(), dn.data());
       if (ps != MS_OK && ps != MS_ETIMEDOUT) {
         fail.store(ps);
         break;
@@ -166,8 +195,12 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
       if (w) std::this_thread::yield();
     }
     for (auto& t : th) t.join();
+    if (rk) {
+      const ms_status ss = ms_resident_stop(rk);
+      if (ss != MS_OK && !fail.load()) fail.store(ss);
+    }
     if (fail.load()) {
-      (void)ms_drain(c, 60ull * 1000000000ull);
+      if (!rk) (void)ms_drain(c, 60ull * 1000000000ull);
       return st ? st : (ms_status)fail.load();
     }
   } else {

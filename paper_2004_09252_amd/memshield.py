@@ -107,6 +107,7 @@ class ms_stats(ctypes.Structure):
 
 MS_SERVE_BATCHED = 0
 MS_SERVE_PLAIN = 1
+MS_SERVE_RESIDENT = 2
 
 
 class ms_serve_trace(ctypes.Structure):
@@ -174,8 +175,14 @@ _SIGS = {
                                    None),
     "ms_resident_start": ([_P, ctypes.POINTER(ms_resident_config),
                            ctypes.c_char_p, ctypes.POINTER(_P)], _I32),
+    "ms_resident_start_keys": ([_P, ctypes.POINTER(ms_resident_config),
+                                ctypes.POINTER(_U64), _U32,
+                                ctypes.POINTER(_P)], _I32),
     "ms_resident_submit": ([_P, _P, _P, _U64, ctypes.POINTER(ms_nonce),
                             ctypes.POINTER(_U64)], _I32),
+    "ms_resident_submit_keyed": ([_P, _U32, _P, _P, _U64,
+                                  ctypes.POINTER(ms_nonce),
+                                  ctypes.POINTER(_U64)], _I32),
     "ms_resident_poll": ([_P, ctypes.POINTER(_U64), ctypes.c_size_t,
                           ctypes.POINTER(_I32), _U64], _I32),
     "ms_resident_alive": ([_P], ctypes.c_int),
@@ -390,10 +397,27 @@ def ms_resident_start(ctx, config: ms_resident_config | None = None,
     return st, r.value
 
 
+def ms_resident_start_keys(ctx, config: ms_resident_config | None, keys):
+    r = ctypes.c_void_p()
+    k = (_U64 * max(len(keys), 1))(*keys)
+    st = _L().ms_resident_start_keys(ctx, ctypes.byref(config)
+                                     if config is not None else None,
+                                     k, len(keys), ctypes.byref(r))
+    return st, r.value
+
+
 def ms_resident_submit(r, src, dst, n_pages, nonce: ms_nonce):
     t = ctypes.c_uint64()
     st = _L().ms_resident_submit(r, src, dst, n_pages, ctypes.byref(nonce),
                                  ctypes.byref(t))
+    return st, t.value
+
+
+def ms_resident_submit_keyed(r, key_index, src, dst, n_pages,
+                             nonce: ms_nonce):
+    t = ctypes.c_uint64()
+    st = _L().ms_resident_submit_keyed(r, key_index, src, dst, n_pages,
+                                       ctypes.byref(nonce), ctypes.byref(t))
     return st, t.value
 
 
@@ -565,18 +589,18 @@ def _nbytes(buf) -> int:
 
 class Resident:
     """A resident-key engine (include/memshield_resident.h) of an Engine.
-    Pages are HostBuffers (pinned, coherent host memory); nonces are
-    linear."""
+    Pages are HostBuffers (pinned, coherent host memory) or device tensors;
+    nonces are linear; `key_index` picks one of the engine's keys."""
 
     def __init__(self, engine, handle: int):
         self.engine, self.handle = engine, handle
 
-    def submit(self, src, dst, nonce, n_pages=None) -> int:
+    def submit(self, src, dst, nonce, n_pages=None, key_index=0) -> int:
         if n_pages is None:
             n_pages = _nbytes(src) // PAGE_SIZE
-        st, t = ms_resident_submit(self.handle, _addr(src), _addr(dst),
-                                   n_pages, nonce)
-        _check(st, "ms_resident_submit")
+        st, t = ms_resident_submit_keyed(self.handle, key_index, _addr(src),
+                                         _addr(dst), n_pages, nonce)
+        _check(st, "ms_resident_submit_keyed")
         return t
 
     def poll(self, tickets, timeout_s: float = 0.0):
@@ -682,14 +706,23 @@ class Engine:
         self._pages(ms_decrypt_pages, "ms_decrypt_pages", key, src, dst, nonce,
                     n_pages, stream)
 
-    def resident(self, key: bytes | None = None, **config) -> Resident:
+    def resident(self, key: bytes | None = None, keys=None,
+                 **config) -> Resident:
+        """Start a resident-key engine with one key (`key` bytes, or a fresh
+        random key) or with `keys`, a list of this engine's key handles."""
         cfg = ms_resident_config_default()
         for k, v in config.items():
             if not hasattr(cfg, k):
                 raise TypeError("unknown resident config field %r" % k)
             setattr(cfg, k, v)
-        st, h = ms_resident_start(self.ctx, cfg, key)
-        _check(st, "ms_resident_start")
+        if keys is not None:
+            if key is not None:
+                raise TypeError("give key bytes or key handles, not both")
+            st, h = ms_resident_start_keys(self.ctx, cfg, list(keys))
+            _check(st, "ms_resident_start_keys")
+        else:
+            st, h = ms_resident_start(self.ctx, cfg, key)
+            _check(st, "ms_resident_start")
         r = Resident(self, h)
         self._residents.append(r)
         return r

@@ -249,10 +249,18 @@ def test_rejections(ms, eng):
     try:
         h = r.handle
         lin = ms.linear_nonce(0, 1, 0)
-        assert ms.ms_resident_submit(h, dev.data_ptr(), host.ptr, 1,
-                                     lin)[0] == ms.MS_EINVAL
         assert ms.ms_resident_submit(h, pageable.ctypes.data, host.ptr, 1,
                                      lin)[0] == ms.MS_EINVAL
+        assert ms.ms_resident_submit(h, host.ptr, pageable.ctypes.data, 1,
+                                     lin)[0] == ms.MS_EINVAL
+        # device memory beyond its allocation, or misaligned
+        assert ms.ms_resident_submit(h, dev.data_ptr(), host.ptr, 5,
+                                     lin)[0] == ms.MS_EINVAL
+        assert ms.ms_resident_submit(h, dev.data_ptr() + 8, host.ptr, 1,
+                                     lin)[0] == ms.MS_EINVAL
+        # a one-key engine holds key index 0 only
+        assert ms.ms_resident_submit_keyed(h, 1, host.ptr, host.ptr, 1,
+                                           lin)[0] == ms.MS_EINVAL
         assert ms.ms_resident_submit(h, host.ptr, host.ptr, 5,
                                      lin)[0] == ms.MS_EINVAL
         assert ms.ms_resident_submit(h, host.ptr, host.ptr + 4096, 2,
@@ -370,3 +378,121 @@ def test_reduced_round_resident_kernels(ms, rounds):
         buf.free()
     finally:
         e.close()
+
+
+def _dev(torch, data):
+    return torch.from_numpy(data.reshape(-1).copy()).to("cuda")
+
+
+@pytest.mark.parametrize("n_pages", [1, 17, 300])
+@pytest.mark.parametrize("in_place", [False, True])
+def test_device_pages_bit_exact(ms, eng, n_pages, in_place):
+    """Pages in HBM go through the same ring: no launch per request."""
+    _note("resident device n_pages=%d in_place=%s" % (n_pages, in_place))
+    import torch
+    rng = np.random.default_rng(7000 + n_pages)
+    key_b = rng.bytes(32)
+    data = workloads.random_pages(rng, n_pages)
+    src = _dev(torch, data)
+    dst = src if in_place else torch.zeros_like(src)
+    r = _start(eng, key_b, workers=128, desc_pages=4)
+    try:
+        r.wait([r.submit(src, dst, ms.linear_nonce(BASE, STRIDE, TAG))])
+        torch.cuda.synchronize()
+        got = dst.cpu().numpy().reshape(n_pages, 4096)
+        assert np.array_equal(got, _want(key_b, data))
+        r.wait([r.submit(dst, dst, ms.linear_nonce(BASE, STRIDE, TAG))])
+        assert np.array_equal(dst.cpu().numpy().reshape(n_pages, 4096), data)
+    finally:
+        r.stop()
+
+
+def test_host_to_device_and_back(ms, eng):
+    """A host page can be ciphered into HBM and an HBM page out to the
+    host: each direction matches the oracle."""
+    _note("resident host<->device")
+    import torch
+    rng = np.random.default_rng(71)
+    key_b = rng.bytes(32)
+    n = 40
+    data = workloads.random_pages(rng, n)
+    host = eng.host_alloc(n * 4096)
+    host.array[:] = data.reshape(-1)
+    dev = torch.zeros(n * 4096, dtype=torch.uint8, device="cuda")
+    r = _start(eng, key_b, workers=64, desc_pages=16)
+    try:
+        r.wait([r.submit(host, dev, ms.linear_nonce(BASE, STRIDE, TAG))])
+        want = _want(key_b, data)
+        assert np.array_equal(dev.cpu().numpy().reshape(n, 4096), want)
+        host.array[:] = 0
+        r.wait([r.submit(dev, host, ms.linear_nonce(BASE, STRIDE, TAG))])
+        assert np.array_equal(host.array.reshape(n, 4096), data)
+    finally:
+        r.stop()
+    host.free()
+
+
+def test_many_keys_from_the_key_table(ms):
+    """An engine started from key handles: key index i ciphers with the
+    i-th handle's key, in any interleaving; its device copy of the keys is
+    wiped; destroying a handle afterwards does not reach the engine."""
+    _note("resident 64 keys")
+    import torch
+    eng = ms.Engine(0)   # a key table of its own: all 64 rows are used
+    rng = np.random.default_rng(72)
+    key_bs = [rng.bytes(32) for _ in range(64)]
+    handles = [eng.key_load(k) for k in key_bs]
+    n = 6
+    picks = [0, 63, 1, 31, 32, 62, 5, 5, 17]
+    data = [workloads.random_pages(rng, n) for _ in picks]
+    src = [_dev(torch, d) for d in data]
+    dst = [torch.zeros_like(s) for s in src]
+    r = eng.resident(keys=handles, workers=96, desc_pages=2,
+                     idle_limit_ms=IDLE_MS)
+    try:
+        assert r.key_wiped() == 1
+        tks = [r.submit(s, o, ms.linear_nonce(BASE + 4096 * 64 * j, STRIDE,
+                                              TAG + j), key_index=k)
+               for j, (k, s, o) in enumerate(zip(picks, src, dst))]
+        r.wait(tks)
+        for j, (k, d, o) in enumerate(zip(picks, data, dst)):
+            want = _want(key_bs[k], d, base=BASE + 4096 * 64 * j,
+                         tag=TAG + j)
+            assert np.array_equal(o.cpu().numpy().reshape(n, 4096), want), j
+        # the same bytes as the launch path with the context's key
+        ref = torch.zeros_like(src[1])
+        eng.encrypt_pages(handles[63], src[1], ref,
+                          ms.linear_nonce(BASE + 4096 * 64, STRIDE, TAG + 1))
+        torch.cuda.synchronize()
+        assert torch.equal(ref, dst[1])
+        assert ms.ms_resident_submit_keyed(r.handle, 64, src[0].data_ptr(),
+                                           src[0].data_ptr(), 1,
+                                           ms.linear_nonce(0, 1, 0))[0] \
+            == ms.MS_EINVAL
+        eng.key_destroy(handles[5])
+        out = torch.zeros_like(src[6])
+        r.wait([r.submit(src[6], out, ms.linear_nonce(BASE + 4096 * 64 * 6,
+                                                      STRIDE, TAG + 6),
+                         key_index=5)])
+        assert torch.equal(out, dst[6])
+    finally:
+        r.stop()
+        eng.close()
+
+
+def test_key_table_start_rejections(ms, eng):
+    _note("resident key table rejections")
+    rng = np.random.default_rng(73)
+    hs = [eng.key_load(rng.bytes(32)) for _ in range(2)]
+    cfg = ms.ms_resident_config_default()
+    cfg.idle_limit_ms = IDLE_MS
+    try:
+        assert ms.ms_resident_start_keys(eng.ctx, cfg, [])[0] == ms.MS_EINVAL
+        assert ms.ms_resident_start_keys(eng.ctx, cfg, hs * 33)[0] == \
+            ms.MS_EINVAL
+        bad = hs[1] ^ (1 << 40)   # a stale generation
+        assert ms.ms_resident_start_keys(eng.ctx, cfg, [hs[0], bad])[0] == \
+            ms.MS_ENOKEY
+    finally:
+        for h in hs:
+            eng.key_destroy(h)

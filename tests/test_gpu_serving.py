@@ -244,10 +244,12 @@ def test_prefetch_hints_run_or_drop(ms):
         eng.close()
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_loadgen_poisson_sample_exact(ms, mode):
     """Poisson arrivals (20k req/s, 0.5 s) through the native load
-    generator; every 25th request's output is checked against the oracle."""
+    generator (continuous batching, a launch per request, the resident-key
+    ring with all 64 client keys); every 25th request's output is checked
+    against the oracle."""
     _note("loadgen mode=%d" % mode)
     import torch
     from paper_2004_09252_amd import serving
