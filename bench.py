@@ -727,7 +727,7 @@ def main():
     ap.add_argument("--serving-duration", type=float, default=10.0)
     ap.add_argument("--serving-pool-pages", type=int, default=2097152)
     ap.add_argument("--sweep-rates", type=float, nargs="*",
-                    default=[20000, 50000, 100000, 200000, 400000])
+                    default=[20000, 50000, 100000, 200000, 400000, 600000])
     ap.add_argument("--sweep-duration", type=float, default=1.0)
     ap.add_argument("--p99-bounds", type=float, nargs="*",
                     default=[50, 75, 100, 200, 500])

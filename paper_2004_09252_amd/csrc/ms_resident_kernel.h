@@ -41,15 +41,16 @@ struct RkHostCtl {
 };
 static_assert(sizeof(RkHostCtl) == 64, "RkHostCtl layout");
 
-// Control words in device memory, zeroed before the launch.
+// Control words in device memory, zeroed before the launch.  The published
+// count, which the waiting workers poll, has a 128-byte line of its own.
 struct RkDevCtl {
-  uint64_t claimed;    // next ring position a worker takes
   uint64_t published;  // the poller's copy of RkHostCtl::published
+  uint64_t pad0[15];
   uint32_t stop;       // poller -> workers
   uint32_t key_loads;  // workers holding the key
-  uint64_t pad[5];
+  uint64_t pad1[15];
 };
-static_assert(sizeof(RkDevCtl) == 64, "RkDevCtl layout");
+static_assert(sizeof(RkDevCtl) == 256, "RkDevCtl layout");
 
 struct RkArgs {
   const RkDesc* ring;     // host, ring_mask + 1 descriptors
@@ -66,6 +67,9 @@ struct RkArgs {
   uint32_t max_pages;     // pages per descriptor
   uint32_t n_keys;        // 1: the key stays in every worker's registers;
                           // 2..kRkMaxKeys: a table in each workgroup's LDS
+  uint32_t inv_step;      // worker w serves the positions congruent to
+                          // w * inv_step modulo n_workers
+  uint32_t pad;
 };
 
 // Kernel entry points (plain C names in the separately built code object),

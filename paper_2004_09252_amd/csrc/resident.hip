@@ -23,8 +23,13 @@
 //     memory or in device memory, its linear nonce, its key index) into a
 //     ring in pinned host memory and publishes a count; the
 //     poller wave reads that count over the link and mirrors it into device
-//     memory, so the idle workers, each holding a claimed ring position,
-//     wait on device memory instead of polling across the link;
+//     memory, so the idle workers wait on device memory instead of polling
+//     across the link;
+//   * each worker owns a fixed share of the ring positions, every W-th (W
+//     workers), so taking work needs no atomic; the shares are strided so
+//     that position q belongs to worker (q mod W) * s mod W, with s >= 4
+//     coprime to W: the pages of one request land in different workgroups,
+//     hence on different compute units and XCDs;
 //   * a worker reads its descriptor and the pages with system-scope loads
 //     (coalesced 8-byte columns, no stale cached copy is possible, whether a
 //     page is in host memory or in HBM), XORs the
@@ -36,7 +41,7 @@
 //     after `idle_ticks` without host activity, and the workers leave when
 //     the poller does, so the launch always drains;
 //   * control flow is wave-uniform everywhere (no lane-masked branches): a
-//     value one lane obtains (a claimed position) comes from an atomic all
+//     value one lane obtains (the key-load count) comes from an atomic all
 //     lanes execute, lane 0 adding 1 and the others 0, and control words are
 //     stored by all lanes with the same value.  A lane-0-only branch next to
 //     a loop back-edge can otherwise be compiled into an exec-mask loop that
@@ -201,7 +206,7 @@ __device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
 
 template <int ROUNDS>
 __device__ void serve_ring(const RkArgs& a, const uint32_t* keytab,
-                           uint4* lds, uint32_t lane) {
+                           uint4* lds, uint32_t lane, uint32_t worker) {
   uint32_t k[8];
   if (a.n_keys == 1) {
 #pragma unroll
@@ -226,11 +231,13 @@ __device__ void serve_ring(const RkArgs& a, const uint32_t* keytab,
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
     st_sys32(&a.hctl->ready, 1u);
   }
-  for (;;) {
+  // this worker's share of the ring: the positions congruent to
+  // worker * inv_step (the inverse of the stride) modulo n_workers
+  // (the product is below n_workers squared, which fits 32 bits, and a
+  // 32-bit division compiles to straight-line code)
+  const uint32_t first = uni((worker * a.inv_step) % a.n_workers);
+  for (uint64_t pos = first;; pos += a.n_workers) {
     if (uni(ld_dev32(&a.dctl->stop))) return;
-    const uint64_t pos = uni64(__hip_atomic_fetch_add(
-        &a.dctl->claimed, lane == 0 ? (uint64_t)1 : (uint64_t)0,
-        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     // wait on device memory until the position is published, or stop; the
     // worker holding the next position to be published polls fastest, the
     // next 63 (the rest of a request of up to 64 descriptors) every ~500
@@ -272,7 +279,7 @@ __device__ __forceinline__ void resident_pages(const RkArgs& a) {
     return;
   }
   if (gw > a.n_workers) return;
-  serve_ring<ROUNDS>(a, keytab, lds[w], lane);
+  serve_ring<ROUNDS>(a, keytab, lds[w], lane, gw - 1);
 }
 
 }  // namespace

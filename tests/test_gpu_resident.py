@@ -496,3 +496,64 @@ def test_key_table_start_rejections(ms, eng):
     finally:
         for h in hs:
             eng.key_destroy(h)
+
+
+def test_device_pages_producers_small_ring(ms):
+    """4 host threads, 200 requests of 1..64 device pages, one descriptor
+    per page, a 128-slot ring and 3 client keys: requests finish out of
+    order, counters and completion slots are reused many times over, and
+    every output matches the oracle."""
+    _note("resident device producers small ring")
+    import torch
+    eng = ms.Engine(0)
+    rng = np.random.default_rng(74)
+    key_bs = [rng.bytes(32) for _ in range(3)]
+    handles = [eng.key_load(k) for k in key_bs]
+    jobs = []
+    for t in range(4):
+        for i in range(50):
+            n = int(rng.integers(1, 65))
+            data = workloads.random_pages(rng, n)
+            k = int(rng.integers(0, 3))
+            base = BASE + 4096 * 100000 * (t * 50 + i)
+            jobs.append((t, n, data, k, base, _dev(torch, data)))
+    outs = {id(j): torch.zeros(j[1] * 4096, dtype=torch.uint8, device="cuda")
+            for j in jobs}
+    torch.cuda.synchronize()
+    r = eng.resident(keys=handles, workers=256, ring_depth=128, desc_pages=1,
+                     idle_limit_ms=IDLE_MS)
+    errors, tickets = [], {}
+
+    def producer(t):
+        try:
+            for j in [j for j in jobs if j[0] == t]:
+                _, n, data, k, base, src = j
+                while True:
+                    try:
+                        tickets[id(j)] = r.submit(
+                            src, outs[id(j)], ms.linear_nonce(base, STRIDE, TAG),
+                            key_index=k)
+                        break
+                    except ms.MemShieldError as e:
+                        if e.status != ms.MS_EAGAIN:
+                            raise
+                        time.sleep(0.0001)
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    try:
+        th = [threading.Thread(target=producer, args=(t,)) for t in range(4)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        assert not errors, errors
+        r.wait(list(tickets.values()))
+        for j in jobs:
+            _, n, data, k, base, _ = j
+            got = outs[id(j)].cpu().numpy().reshape(n, 4096)
+            assert np.array_equal(got, _want(key_bs[k], data, base=base)), \
+                (n, k, base)
+    finally:
+        r.stop()
+        eng.close()
