@@ -38,6 +38,7 @@
 #include "ms_internal.h"
 #include "ms_kernels.h"
 #include "ms_resident_kernel.h"
+#include "resident_shares.h"
 
 static_assert(ms::kRkMaxKeys == MS_RESIDENT_MAX_KEYS, "key table size");
 
@@ -178,27 +179,6 @@ hsa_status_t match_agent(hsa_agent_t a, void* data) {
     return HSA_STATUS_INFO_BREAK;
   }
   return HSA_STATUS_SUCCESS;
-}
-
-// The stride of the workers' shares of the ring: the smallest s >= 4
-// coprime to `workers` (consecutive positions then fall in different
-// workgroups of 4 waves), and its inverse modulo `workers`.
-uint32_t share_stride_inverse(uint32_t workers) {
-  if (workers <= 1) return 0;
-  auto gcd = [](uint64_t x, uint64_t y) {
-    while (y) {
-      const uint64_t t = x % y;
-      x = y;
-      y = t;
-    }
-    return x;
-  };
-  uint64_t step = 4;
-  while (gcd(step, workers) != 1) ++step;
-  step %= workers;
-  for (uint64_t inv = 1; inv < workers; ++inv)
-    if (step * inv % workers == 1) return (uint32_t)inv;
-  return 1;  // not reached: step is a unit modulo workers
 }
 
 const char* kernel_symbol(int rounds) {
@@ -459,7 +439,7 @@ ms_status start_engine(ms_ctx* c, const ms_resident_config* cfg_in,
   a.n_workers = r->workers;
   a.max_pages = cfg.desc_pages;
   a.n_keys = n_keys;
-  a.inv_step = share_stride_inverse(r->workers);
+  a.inv_step = ms::share_stride_inverse(r->workers);
   st = dispatch(r, a, rounds);
   if (st) {
     release(r);
