@@ -6,10 +6,11 @@
 // lane l of the wave: A row (l % 16), K elements 4*(l/16)..+3; B column
 // (l % 16), K elements 4*(l/16)..+3; accumulator column (l % 16), rows
 // 4*(l/16)..+3.  A workgroup of four waves computes a 64x64 output tile,
-// each wave a 32x32 quarter (2x2 MFMA tiles), staging 64x32 / 32x64 bf16
-// tiles of A and B through LDS per K step of 32.  Transposed operands are
-// handled in the LDS staging, so one kernel serves the forward products and
-// both gradient products.  The epilogue adds a bias, applies ReLU or a ReLU
+// each wave a 32x32 quarter (2x2 MFMA tiles), staging 64x128 bf16 tiles of A
+// and B through LDS per K step of 128: four 16-byte global loads per
+// operand and thread, the next step's loads in flight during the current
+// step's MFMAs.  Transposed operands are handled in the LDS staging, so one kernel
+// serves the forward products and both gradient products.  The epilogue adds a bias, applies ReLU or a ReLU
 // mask taken from a stored activation, and writes float32 and/or bf16.
 //
 // Everything else (embedding gather and its deterministic scatter-add,
@@ -29,7 +30,7 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 64;
-constexpr int kTileK = 32;
+constexpr int kTileK = 128;
 
 __device__ __forceinline__ float bf2f(uint16_t h) {
   return __uint_as_float((uint32_t)h << 16);
@@ -54,62 +55,161 @@ struct GemmArgs {
   int transA, transB, relu;
 };
 
+// Eight consecutive bf16 of a row starting at p, of which `valid` (0..8)
+// lie inside the matrix (the rest read as zero): one 16-byte load when all
+// eight are inside and the row is 16-byte aligned, element loads otherwise.
+__device__ __forceinline__ uint4 load8(const uint16_t* p, int valid,
+                                       bool vec) {
+  if (vec && valid == 8) return *reinterpret_cast<const uint4*>(p);
+  uint16_t e[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) e[i] = i < valid ? p[i] : (uint16_t)0;
+  return make_uint4(e[0] | (uint32_t)e[1] << 16, e[2] | (uint32_t)e[3] << 16,
+                    e[4] | (uint32_t)e[5] << 16, e[6] | (uint32_t)e[7] << 16);
+}
+
+__device__ __forceinline__ int clamp8(int64_t left) {
+  return left <= 0 ? 0 : (left >= 8 ? 8 : (int)left);
+}
+
+__device__ __forceinline__ uint16_t half_of(const uint4& v, int i) {
+  const uint32_t w = i < 2 ? v.x : (i < 4 ? v.y : (i < 6 ? v.z : v.w));
+  return (uint16_t)(w >> (16 * (i & 1)));
+}
+
+// Both LDS tiles hold their K dimension contiguous (A as [m][k], B as
+// [n][k]), so an MFMA operand (4 consecutive k) is one 8-byte LDS read.  A
+// row is kTileK k plus 8 of padding, which spreads the rows a wave reads at
+// once over the LDS banks.
+constexpr int kLdsRow = kTileK + 8;
+// 8-element chunks per operand tile (64 x kTileK) and per thread
+constexpr int kChunks = kTile * kTileK / 8 / 256;
+static_assert(kChunks * 256 * 8 == kTile * kTileK, "tile split");
+
+// Workgroup barrier for the LDS tiles only: the LDS accesses before it are
+// complete (lgkmcnt) and visible after it, while global loads stay in
+// flight across it.  __syncthreads() would also wait for every outstanding
+// global load (it is a fence as well), which drains the next step's
+// prefetch at each step.  The memory clobber keeps the compiler from moving
+// LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" : : : "memory");
+}
+
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
-  __shared__ uint16_t As[kTile][kTileK + 8];
-  __shared__ uint16_t Bs[kTileK][kTile + 8];
+  __shared__ __align__(16) uint16_t As[kTile][kLdsRow];
+  __shared__ __align__(16) uint16_t Bt[kTile][kLdsRow];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
   const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
+  // 16-byte global loads need 16-byte aligned rows
+  const bool vecA = (reinterpret_cast<uintptr_t>(g.A) & 15) == 0 &&
+                    (g.lda & 7) == 0;
+  const bool vecB = (reinterpret_cast<uintptr_t>(g.B) & 15) == 0 &&
+                    (g.ldb & 7) == 0;
+  // Each thread moves kChunks 8-element chunks of A and of B per K step,
+  // along the dimension that is contiguous in memory; chunk c = tid + 256j
+  // of a tile of 64 rows (m or n) by kTileK k is, with R = kTileK / 8:
+  //   A [m][k], B^T [n][k] (k contiguous): row c / R, k 8 * (c % R); one
+  //     16-byte LDS store;
+  //   A^T [k][m], B [k][n] (m or n contiguous): k c % kTileK, rows
+  //     8 * (c / kTileK) + 0..7; eight 2-byte LDS stores, and since a wave's
+  //     lanes hold 64 consecutive k of the same rows, each of those stores
+  //     spreads over all the LDS banks.
+  constexpr int R = kTileK / 8;
+  uint4 ra[kChunks], rb[kChunks];
+  auto fetch = [&](int k0) {
+    // A tile wholly inside both matrices, with 16-byte aligned rows, takes
+    // straight-line 16-byte loads; the test is uniform across the
+    // workgroup, so no lane waits on another's element loads
+    const bool interior = vecA && vecB && m0 + kTile <= g.M &&
+                          n0 + kTile <= g.N && k0 + kTileK <= g.K;
+    if (interior) {
+#pragma unroll
+      for (int j = 0; j < kChunks; ++j) {
+        const int c = tid + 256 * j;
+        const int64_t ao =
+            !g.transA ? (int64_t)(m0 + c / R) * g.lda + k0 + 8 * (c % R)
+                      : (int64_t)(k0 + c % kTileK) * g.lda + m0 +
+                            8 * (c / kTileK);
+        const int64_t bo =
+            !g.transB ? (int64_t)(k0 + c % kTileK) * g.ldb + n0 +
+                            8 * (c / kTileK)
+                      : (int64_t)(n0 + c / R) * g.ldb + k0 + 8 * (c % R);
+        ra[j] = *reinterpret_cast<const uint4*>(g.A + ao);
+        rb[j] = *reinterpret_cast<const uint4*>(g.B + bo);
+      }
+      return;
+    }
+#pragma unroll
+    for (int j = 0; j < kChunks; ++j) {
+      const int c = tid + 256 * j;
+      if (!g.transA) {
+        const int64_t m = m0 + c / R, k = k0 + 8 * (c % R);
+        const int valid = m < g.M ? clamp8(g.K - k) : 0;
+        ra[j] = load8(g.A + (valid ? m * g.lda + k : 0), valid, vecA);
+      } else {
+        const int64_t k = k0 + c % kTileK, m = m0 + 8 * (c / kTileK);
+        const int valid = k < g.K ? clamp8(g.M - m) : 0;
+        ra[j] = load8(g.A + (valid ? k * g.lda + m : 0), valid, vecA);
+      }
+      if (!g.transB) {
+        const int64_t k = k0 + c % kTileK, n = n0 + 8 * (c / kTileK);
+        const int valid = k < g.K ? clamp8(g.N - n) : 0;
+        rb[j] = load8(g.B + (valid ? k * g.ldb + n : 0), valid, vecB);
+      } else {
+        const int64_t n = n0 + c / R, k = k0 + 8 * (c % R);
+        const int valid = n < g.N ? clamp8(g.K - k) : 0;
+        rb[j] = load8(g.B + (valid ? n * g.ldb + k : 0), valid, vecB);
+      }
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int j = 0; j < kChunks; ++j) {
+      const int c = tid + 256 * j;
+      if (!g.transA) {
+        *reinterpret_cast<uint4*>(&As[c / R][8 * (c % R)]) = ra[j];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          As[8 * (c / kTileK) + i][c % kTileK] = half_of(ra[j], i);
+      }
+      if (g.transB) {
+        *reinterpret_cast<uint4*>(&Bt[c / R][8 * (c % R)]) = rb[j];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          Bt[8 * (c / kTileK) + i][c % kTileK] = half_of(rb[j], i);
+      }
+    }
+  };
   v4f acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
 
+  fetch(0);
   for (int k0 = 0; k0 < g.K; k0 += kTileK) {
-#pragma unroll
-    for (int t = 0; t < (kTile * kTileK) / 256; ++t) {
-      const int idx = tid + 256 * t;
-      int m, k;
-      if (g.transA) { m = idx % kTile; k = idx / kTile; }
-      else { m = idx / kTileK; k = idx % kTileK; }
-      const int gm = m0 + m, gk = k0 + k;
-      uint16_t v = 0;
-      if (gm < g.M && gk < g.K)
-        v = g.transA ? g.A[(size_t)gk * g.lda + gm] : g.A[(size_t)gm * g.lda + gk];
-      As[m][k] = v;
-    }
-#pragma unroll
-    for (int t = 0; t < (kTile * kTileK) / 256; ++t) {
-      const int idx = tid + 256 * t;
-      int k, n;
-      if (g.transB) { n = idx / kTileK; k = idx % kTileK; }
-      else { k = idx / kTile; n = idx % kTile; }
-      const int gn = n0 + n, gk = k0 + k;
-      uint16_t v = 0;
-      if (gn < g.N && gk < g.K)
-        v = g.transB ? g.B[(size_t)gn * g.ldb + gk] : g.B[(size_t)gk * g.ldb + gn];
-      Bs[k][n] = v;
-    }
-    __syncthreads();
+    stash();
+    lds_barrier();
+    // the next step's global loads are in flight during this step's MFMAs
+    if (k0 + kTileK < g.K) fetch(k0 + kTileK);
 #pragma unroll
     for (int kk = 0; kk < kTileK; kk += 16) {
       const int kb = kk + 4 * (lane >> 4);
       v4s a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int r = wm * 32 + i * 16 + (lane & 15);
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const v4s*>(
+            &As[wm * 32 + i * 16 + (lane & 15)][kb]);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) a[i][t] = (short)As[r][kb + t];
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int c = wn * 32 + j * 16 + (lane & 15);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) b[j][t] = (short)Bs[kb + t][c];
-      }
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const v4s*>(
+            &Bt[wn * 32 + j * 16 + (lane & 15)][kb]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -117,7 +217,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
               a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
+    lds_barrier();
   }
 
 #pragma unroll
