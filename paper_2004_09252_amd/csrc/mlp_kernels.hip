@@ -254,13 +254,12 @@ __global__ void embed_gather_kernel(const uint16_t* __restrict__ E,
   }
 }
 
-// dE[v][d] = sum over (b, s) with ids[b][s] == v of dx[b][s*D + d], summed in
-// (b, s) order: one workgroup per vocabulary row, deterministic.
 // dE[v][d] = sum over positions i, in increasing order, with ids[i] == v of
-// dx[i][d].  One wave per embedding row: each step tests 64 positions at
-// once and the matching ones, found with a ballot, are added lowest first,
-// so the sum has a fixed order (deterministic) without scanning the
-// positions one at a time.
+// dx[i][d].  One wave per embedding row: it tests 64 positions at once and
+// adds the matching ones, found with a ballot, lowest first, so the sum has
+// a fixed order (deterministic) without scanning the positions one at a
+// time.  Loads are batched (512 ids, then up to 8 matching rows of dx, in
+// flight together) so the scan is not one memory round trip per step.
 __global__ __launch_bounds__(64) void embed_scatter_kernel(
     const float* __restrict__ dx, const int32_t* __restrict__ ids, int B,
     int C, int D, int V, float* __restrict__ dE) {
@@ -270,18 +269,38 @@ __global__ __launch_bounds__(64) void embed_scatter_kernel(
   for (int d0 = 0; d0 < D; d0 += 64) {
     const int d = d0 + lane;
     float acc = 0.f;
-    for (int base = 0; base < n; base += 64) {
-      const int i = base + lane;
-      int id = -1;
-      if (i < n) {
-        id = ids[i];
-        id = id < 0 ? 0 : (id >= V ? V - 1 : id);
+    // ids 512 at a time: eight independent 64-id loads in flight, then the
+    // eight ballots in position order
+    for (int base = 0; base < n; base += 512) {
+      int id[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = base + 64 * q + lane;
+        const int x = ids[i < n ? i : n - 1];
+        id[q] = i < n ? (x < 0 ? 0 : (x >= V ? V - 1 : x)) : -1;
       }
-      unsigned long long m = __ballot(id == v);
-      while (m) {
-        const int j = __ffsll(m) - 1;
-        m &= m - 1;
-        if (d < D) acc += dx[(int64_t)(base + j) * D + d];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        unsigned long long m = __ballot(id[q] == v);
+        // matches up to 8 at a time: their dx loads issued together, then
+        // added in ascending position, the same order as one by one
+        while (m) {
+          int pos[8];
+          int cnt = 0;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            pos[t] = m ? base + 64 * q + __ffsll(m) - 1 : 0;
+            cnt += m ? 1 : 0;
+            m &= m - 1;
+          }
+          float val[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            val[t] = (t < cnt && d < D) ? dx[(int64_t)pos[t] * D + d] : 0.f;
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (t < cnt) acc += val[t];
+        }
       }
     }
     if (d < D) dE[(int64_t)v * D + d] = acc;
@@ -348,23 +367,51 @@ __global__ void mean_kernel(const float* __restrict__ v, int n,
 // its 16 waves sum the rows g, g+16, g+32, ... of each column, and the 16
 // partial sums are added in a fixed tree order (deterministic).
 constexpr int kColsumGroups = 16;
-__global__ __launch_bounds__(64 * kColsumGroups) void colsum_kernel(
+constexpr int kColsumMaxSlices = 32;
+
+// Row slices for a column sum over M rows: enough to fill the device with
+// (N / 64) x slices workgroups, each slice at least 64 rows.
+int colsum_slices(int M) {
+  const int s = (M + 63) / 64;
+  return s < 1 ? 1 : (s > kColsumMaxSlices ? kColsumMaxSlices : s);
+}
+
+// Partial column sums: workgroup (x, s) sums rows [s*R, (s+1)*R) (R =
+// ceil(M / slices)) of columns 64x..64x+63 into part[s][n].  Sixteen waves
+// take rows g, g+16, ... of the slice; an LDS tree in fixed order combines
+// them.
+__global__ __launch_bounds__(64 * kColsumGroups) void colsum_partial_kernel(
     const float* __restrict__ in, int M, int N, int ld,
-    float* __restrict__ out) {
-  __shared__ float part[kColsumGroups][64];
+    float* __restrict__ part) {
+  __shared__ float acc[kColsumGroups][64];
   const int c = threadIdx.x & 63;
   const int g = threadIdx.x >> 6;
   const int n = blockIdx.x * 64 + c;
+  const int rows = (M + gridDim.y - 1) / gridDim.y;
+  const int r0 = blockIdx.y * rows;
+  const int r1 = r0 + rows < M ? r0 + rows : M;
   float s = 0.f;
   if (n < N)
-    for (int m = g; m < M; m += kColsumGroups) s += in[(int64_t)m * ld + n];
-  part[g][c] = s;
+    for (int m = r0 + g; m < r1; m += kColsumGroups)
+      s += in[(int64_t)m * ld + n];
+  acc[g][c] = s;
   __syncthreads();
   for (int k = kColsumGroups / 2; k > 0; k >>= 1) {
-    if (g < k) part[g][c] += part[g + k][c];
+    if (g < k) acc[g][c] += acc[g + k][c];
     __syncthreads();
   }
-  if (g == 0 && n < N) out[n] = part[0][c];
+  if (g == 0 && n < N) part[(int64_t)blockIdx.y * N + n] = acc[0][c];
+}
+
+// out[n] = part[0][n] + part[1][n] + ... in slice order (deterministic).
+__global__ __launch_bounds__(256) void colsum_final_kernel(
+    const float* __restrict__ part, int slices, int N,
+    float* __restrict__ out) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int i = 0; i < slices; ++i) s += part[(int64_t)i * N + n];
+  out[n] = s;
 }
 
 __global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m,
@@ -398,6 +445,12 @@ __global__ void to_bf16_kernel(const float* __restrict__ s,
 // order is (value descending, id ascending); NaN counts as -inf.  With
 // `prob` set, also the softmax probability of each chosen id over the whole
 // row.
+// a ranks before b: larger value, or the same value and a lower index
+__device__ __forceinline__ bool ranks_before(float av, int ai, float bv,
+                                             int bi) {
+  return av > bv || (av == bv && ai < bi);
+}
+
 __global__ __launch_bounds__(64) void topk_kernel(
     const float* __restrict__ logits, int V, int k, int exclude,
     int32_t* __restrict__ out, float* __restrict__ prob) {
@@ -412,25 +465,50 @@ __global__ __launch_bounds__(64) void topk_kernel(
     for (int i = lane; i < V; i += 64) sum += expf(row[i] - mx);
     for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
   }
-  int chosen[16];
-  for (int r = 0; r < k; ++r) {
-    float bv = -INFINITY;
-    int bi = 0x7fffffff;
-    for (int i = lane; i < V; i += 64) {
-      if (i == exclude) continue;
-      bool used = false;
-      for (int q = 0; q < r; ++q) used |= chosen[q] == i;
-      if (used) continue;
-      float x = row[i];
-      if (x != x) x = -INFINITY;
-      if (x > bv || (x == bv && i < bi)) { bv = x; bi = i; }
+  // One pass over the row: each lane keeps the best 16 of its positions
+  // lane, lane + 64, ... (NaN counts as -inf, `exclude` is skipped) sorted
+  // in registers; an entry enters by swapping down the list.  The best k
+  // of the row are the best k of the lanes' lists.
+  float lv[16];
+  int li[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    lv[t] = -INFINITY;
+    li[t] = 0x7fffffff;
+  }
+  for (int i = lane; i < V; i += 64) {
+    if (i == exclude) continue;
+    float cv = row[i];
+    if (cv != cv) cv = -INFINITY;
+    int ci = i;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const bool before = ranks_before(cv, ci, lv[t], li[t]);
+      const float tv = lv[t];
+      const int ti = li[t];
+      lv[t] = before ? cv : tv;
+      li[t] = before ? ci : ti;
+      cv = before ? tv : cv;
+      ci = before ? ti : ci;
     }
+  }
+  // k rounds: the best list head over the wave, popped by its lane
+  for (int r = 0; r < k; ++r) {
+    float bv = lv[0];
+    int bi = li[0];
     for (int off = 32; off > 0; off >>= 1) {
       const float ov = __shfl_xor(bv, off, 64);
       const int oi = __shfl_xor(bi, off, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      if (ranks_before(ov, oi, bv, bi)) { bv = ov; bi = oi; }
     }
-    chosen[r] = bi;
+    const bool mine = li[0] == bi;
+#pragma unroll
+    for (int t = 0; t < 15; ++t) {
+      lv[t] = mine ? lv[t + 1] : lv[t];
+      li[t] = mine ? li[t + 1] : li[t];
+    }
+    lv[15] = mine ? -INFINITY : lv[15];
+    li[15] = mine ? 0x7fffffff : li[15];
     if (lane == 0) {
       out[(int64_t)b * k + r] = bi;
       if (prob) prob[(int64_t)b * k + r] = expf(bv - mx) / sum;
@@ -451,7 +529,7 @@ bool shape_ok(const ms_mlp_shape* s) {
 
 struct Ws {
   uint16_t *x, *h1, *h2, *dlH, *dz2H, *dz1H;
-  float *logits, *dlF, *dz2F, *dz1F, *dxF, *row_loss;
+  float *logits, *dlF, *dz2F, *dz1F, *dxF, *row_loss, *colpart;
   uint64_t bytes;
 };
 
@@ -477,8 +555,23 @@ Ws carve(const ms_mlp_shape* s, int64_t Bm, uint8_t* base) {
   w.dz1F = (float*)take(Bm * H * 4);
   w.dxF = (float*)take(Bm * CD * 4);
   w.row_loss = (float*)take(Bm * 4);
+  w.colpart = (float*)take((uint64_t)kColsumMaxSlices * (V > H ? V : H) * 4);
   w.bytes = off;
   return w;
+}
+
+// Column sums of an M x N float32 matrix (leading dimension ld) into out,
+// through per-slice partial sums in `part` (kColsumMaxSlices x N floats).
+hipError_t colsum(const float* in, int M, int N, int ld, float* out,
+                  float* part, hipStream_t st) {
+  const int slices = colsum_slices(M);
+  hipLaunchKernelGGL(colsum_partial_kernel, dim3((N + 63) / 64, slices),
+                     dim3(64 * kColsumGroups), 0, st, in, M, N, ld, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 255) / 256), dim3(256), 0,
+                     st, part, slices, N, out);
+  return hipGetLastError();
 }
 
 hipError_t gemm(const GemmArgs& g, hipStream_t s) {
@@ -581,9 +674,8 @@ ms_status ms_mlp_backward(const ms_mlp_shape* s, const uint16_t* P,
   GemmArgs g = gemm_args(w.h2, H, 1, w.dlH, V, 0, H, V, B);
   g.outF = G + off[5]; g.ldo = V;
   if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
-  hipLaunchKernelGGL(colsum_kernel, dim3((V + 63) / 64),
-                     dim3(64 * kColsumGroups), 0, st,
-                     w.dlF, B, V, V, G + off[6]);
+  if (colsum(w.dlF, B, V, V, G + off[6], w.colpart, st) != hipSuccess)
+    return MS_EDEVICE;
   g = gemm_args(w.dlH, V, 0, P + off[5], V, 1, B, H, V);
   g.mask = w.h2; g.ldm = H; g.outF = w.dz2F; g.ldo = H; g.outH = w.dz2H;
   g.ldh = H;
@@ -592,9 +684,8 @@ ms_status ms_mlp_backward(const ms_mlp_shape* s, const uint16_t* P,
   g = gemm_args(w.h1, H, 1, w.dz2H, H, 0, H, H, B);
   g.outF = G + off[3]; g.ldo = H;
   if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
-  hipLaunchKernelGGL(colsum_kernel, dim3((H + 63) / 64),
-                     dim3(64 * kColsumGroups), 0, st,
-                     w.dz2F, B, H, H, G + off[4]);
+  if (colsum(w.dz2F, B, H, H, G + off[4], w.colpart, st) != hipSuccess)
+    return MS_EDEVICE;
   g = gemm_args(w.dz2H, H, 0, P + off[3], H, 1, B, H, H);
   g.mask = w.h1; g.ldm = H; g.outF = w.dz1F; g.ldo = H; g.outH = w.dz1H;
   g.ldh = H;
@@ -603,9 +694,8 @@ ms_status ms_mlp_backward(const ms_mlp_shape* s, const uint16_t* P,
   g = gemm_args(w.x, CD, 1, w.dz1H, H, 0, CD, H, B);
   g.outF = G + off[1]; g.ldo = H;
   if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
-  hipLaunchKernelGGL(colsum_kernel, dim3((H + 63) / 64),
-                     dim3(64 * kColsumGroups), 0, st,
-                     w.dz1F, B, H, H, G + off[2]);
+  if (colsum(w.dz1F, B, H, H, G + off[2], w.colpart, st) != hipSuccess)
+    return MS_EDEVICE;
   g = gemm_args(w.dz1H, H, 0, P + off[1], H, 1, B, CD, H);
   g.outF = w.dxF; g.ldo = CD;
   if (gemm(g, st) != hipSuccess) return MS_EDEVICE;

@@ -117,14 +117,22 @@ def test_topk_exact_on_gpu_logits(pred):
     ids = rng.integers(0, SHAPE["vocab"], size=(300, SHAPE["context"]))
     logits = pred.forward(ids)
     host = logits.cpu().numpy()
-    # plant ties
+    # plant ties: across lanes at the top of row 0; everywhere in row 1
+    # (values on a coarse grid, so positions 64 apart, which one lane scans,
+    # tie too); row 2 all equal (the answer is then ids 0..k-1)
     host[0, 10] = host[0, 20] = host[0, 30] = host[0].max() + 1.0
+    host[1] = np.floor(host[1] * 2.0) / 2.0
+    host[2] = 0.25
     logits.copy_(__import__("torch").from_numpy(host))
     got, prob = pred.topk(logits, 8, SHAPE["vocab"] - 1, with_prob=True)
     got = got.cpu().numpy()
     want = mlp_ref.topk_ids(host, 8, exclude=SHAPE["vocab"] - 1)
     assert np.array_equal(got, want)
     assert got[0, :3].tolist() == [10, 20, 30]
+    assert got[2].tolist() == list(range(8))
+    got16 = pred.topk(logits, 16, 3)
+    assert np.array_equal(got16.cpu().numpy(),
+                          mlp_ref.topk_ids(host, 16, exclude=3))
     h64 = host.astype(np.float64)
     sm = np.exp(h64 - h64.max(axis=1, keepdims=True))
     sm /= sm.sum(axis=1, keepdims=True)
