@@ -83,8 +83,11 @@ class _Reqs:
 
 def test_alone_equals_mix_equals_oracle(ms):
     """Each request's result is the same submitted alone (one at a time,
-    waiting for each) and in the mix (all submitted concurrently from 8
-    threads, batched by the scheduler)."""
+    waiting for each) and in the mix (submitted concurrently from 8
+    threads, 12 requests per call, batched by the scheduler).  A call's
+    requests are queued together, so every launch serves at least one
+    call's worth: the batching does not depend on how fast the device
+    finishes a request before the next call arrives."""
     _note("alone vs mix, 96 requests")
     eng = ms.Engine(0)
     try:
@@ -97,8 +100,10 @@ def test_alone_equals_mix_equals_oracle(ms):
         tickets = [None] * 96
 
         def submitter(k):
-            for i in range(k, 96, 8):
-                tickets[i] = eng.submit([r.req(i, r.dst_b)])[0]
+            mine = list(range(k, 96, 8))
+            got = eng.submit([r.req(i, r.dst_b) for i in mine])
+            for i, t in zip(mine, got):
+                tickets[i] = t
 
         th = [threading.Thread(target=submitter, args=(k,)) for k in range(8)]
         for t in th:
@@ -108,8 +113,8 @@ def test_alone_equals_mix_equals_oracle(ms):
         st, done = eng.poll(tickets, timeout_s=60)
         assert st == 0 and all(d == 1 for d in done)
         after = eng.stats()
-        # the mix was served by fewer fused launches than requests
-        assert after.batches - before.batches < 96
+        # the mix was served by fused launches of at least one call each
+        assert after.batches - before.batches <= 8
         assert after.max_batch_requests > 1
         for i in range(96):
             a = r.slice(r.dst_a, i)
