@@ -594,6 +594,45 @@ def run_serving(args, ms, torch):
     return out
 
 
+def run_predictor(args, ms, torch):
+    """The delta predictor's training and inference alone: Adam steps of
+    batch 1024 (context 16, embed 64, hidden 256, 1024 delta ids) on seeded
+    uniform delta ids of the workload's shape, and top-8 predictions for 64
+    and 1024 rows, timed after a warm-up with the device synchronized."""
+    import time
+    import numpy as np
+    from paper_2004_09252_amd import prefetch
+    from paper_2004_09252_amd.predictor import Predictor
+    p = Predictor(max_batch=1024, seed=1)
+    rng = np.random.default_rng(7)
+    xs = rng.integers(0, p.vocab, size=(65536, p.context)).astype(np.int32)
+    ys = rng.integers(0, p.vocab, size=65536).astype(np.int32)
+    prefetch.train(p, xs, ys, steps=20, batch=1024)
+    torch.cuda.synchronize()
+    steps = args.predictor_steps
+    t0 = time.perf_counter()
+    prefetch.train(p, xs, ys, steps=steps, batch=1024, seed=1)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    out = {"what": "Adam steps of batch 1024 on uniform delta ids (context "
+                   "16, embed 64, hidden 256, vocab 1024); top-8 with "
+                   "probabilities",
+           "train_steps": steps,
+           "train_ms_per_step": round(train_s / steps * 1e3, 4)}
+    for rows in (64, 1024):
+        ids = torch.from_numpy(xs[:rows]).to("cuda")
+        for _ in range(5):
+            p.predict(ids, 8, p.vocab - 1, with_prob=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(100):
+            p.predict(ids, 8, p.vocab - 1, with_prob=True)
+        torch.cuda.synchronize()
+        out["predict_%d_rows_ms" % rows] = round(
+            (time.perf_counter() - t0) / 100 * 1e3, 4)
+    return out
+
+
 def run_prefetch(args, ms, torch):
     """Learned pre-decryption on the 2M-access trace (64 clients x 1024
     pages): train on the fault events of the first 80%, then compare, over
@@ -743,6 +782,10 @@ def main():
     ap.add_argument("--prefetch-window", type=int, default=8)
     ap.add_argument("--prefetch-train-steps", type=int, default=1500)
     ap.add_argument("--prefetch-min-prob", type=float, default=0.1)
+    ap.add_argument("--predictor-only", action="store_true",
+                    help="time only the predictor's training steps and "
+                         "predictions (one JSON object)")
+    ap.add_argument("--predictor-steps", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the page cipher needs no "
@@ -757,6 +800,10 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     ms.load_library()
+    if args.predictor_only:
+        print(json.dumps({"predictor": run_predictor(args, ms, torch)}),
+              flush=True)
+        return
 
     log("generating bulk workload (%d pages)" % args.pages)
     b = workloads.bulk(seed=2, n_pages=args.pages)

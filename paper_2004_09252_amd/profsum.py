@@ -3,6 +3,8 @@
 Usage (from the repository root, on the databases a profiling run left):
 
     python -m paper_2004_09252_amd.profsum trace  <trace.db>  <out.md>  <cmd>
+    python -m paper_2004_09252_amd.profsum trace-titled <title> <trace.db> \
+        <out.md> <cmd>
     python -m paper_2004_09252_amd.profsum traffic <fetch.db> <write.db> \
         <out.txt> <cmd-fetch> <cmd-write>
     python -m paper_2004_09252_amd.profsum valu <valu.db> <out.txt> <cmd>
@@ -45,13 +47,14 @@ def _short(name: str) -> str:
     return name if len(name) <= 90 else name[:87] + "..."
 
 
-def trace(db_path: str, out_path: str, cmd: str) -> None:
+def trace(db_path: str, out_path: str, cmd: str,
+          title: str = "page-cipher benchmark") -> None:
     db = sqlite3.connect(db_path)
     groups = collections.defaultdict(list)
     for name, gx, wx, dur in db.execute(
             "select name, grid_x, workgroup_x, duration from kernels"):
         groups[(name, gx // max(wx, 1))].append(dur)
-    lines = ["# rocprofv3 kernel trace: page-cipher benchmark", "",
+    lines = ["# rocprofv3 kernel trace: " + title, "",
              "Command (from the repository root, after `cd /tmp && export "
              "TMPDIR=/tmp`):", "", "    " + cmd, "",
              "Durations in microseconds; `blocks` is the grid size in "
@@ -222,6 +225,9 @@ def main(argv):
         return 0
     if len(argv) >= 5 and argv[1] == "valu":
         valu(argv[2], argv[3], " ".join(argv[4:]))
+        return 0
+    if len(argv) >= 6 and argv[1] == "trace-titled":
+        trace(argv[3], argv[4], " ".join(argv[5:]), title=argv[2])
         return 0
     if len(argv) >= 5 and argv[1] == "trace":
         trace(argv[2], argv[3], " ".join(argv[4:]))
