@@ -100,13 +100,25 @@ def cpu_baseline(b, n_pages_sample: int, reps: int):
     dt = time.perf_counter() - t0
     assert np.array_equal(dec, data)
     gbs = reps * 2 * n_pages_sample * 4096 / dt / 1e9
+    # the same oracle on one thread, over the first 128 MiB
+    n1 = min(n_pages_sample, 32768)
+    t0 = time.perf_counter()
+    enc1, _ = oracle.cipher_pages_timed(b.key, nonces[:n1], data[:n1],
+                                        threads=1)
+    dec1, _ = oracle.cipher_pages_timed(b.key, nonces[:n1], enc1, threads=1)
+    dt1 = time.perf_counter() - t0
+    assert np.array_equal(dec1, data[:n1])
     return {"value": round(gbs, 4), "unit": "GB/s", "cores": int(used),
             "kind": "oracle",
             "sample": "%d x (encrypt + decrypt) of the first %d pages "
                       "(%d MiB) of the bulk workload, scalar C oracle, "
                       "%d threads, %.1f s wall" % (
                           reps, n_pages_sample, n_pages_sample // 256,
-                          used, dt)}
+                          used, dt),
+            "single_thread": {
+                "GBps": round(2 * n1 * 4096 / dt1 / 1e9, 4),
+                "sample": "encrypt + decrypt of the first %d pages (%d MiB), "
+                          "1 thread, %.2f s wall" % (n1, n1 // 256, dt1)}}
 
 
 def run_bulk(args, ms, torch, b):
