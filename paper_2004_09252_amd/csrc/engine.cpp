@@ -593,8 +593,15 @@ void scheduler_main(ms_ctx* c) {
   (void)hipSetDevice(c->device);
   auto last_work = Clock::now();
   for (;;) {
-    bool did = false, idle_device = false;
-    {
+    bool did = false, idle_device = true, queues_empty = true;
+    // `outstanding` counts requests queued or in flight (a batch's until it
+    // is reaped): at zero there is nothing to launch or reap, and the
+    // scheduler leaves sched_mu alone, so that a submitting thread finds it
+    // free and launches on an idle device itself.  A submission raises the
+    // count before it queues, so one the submitter could not launch is seen
+    // here on the next pass.
+    const bool any = c->outstanding.load(std::memory_order_acquire) != 0;
+    if (any) {
       std::lock_guard<std::mutex> lk(c->sched_mu);
       did = reap(c);
       while (launch_one(c)) did = true;
@@ -604,8 +611,7 @@ void scheduler_main(ms_ctx* c) {
       last_work = Clock::now();
       continue;
     }
-    bool queues_empty;
-    {
+    if (any) {
       std::lock_guard<std::mutex> lk(c->q_mu);
       queues_empty = c->demand_q.empty() && c->prefetch_q.empty();
     }
@@ -622,7 +628,9 @@ void scheduler_main(ms_ctx* c) {
       continue;
     }
     // idle: keep polling for a while (a thread woken from a sleep costs
-    // tens of microseconds), then sleep until a submission
+    // tens of microseconds), then sleep until a submission.  The wake-up
+    // test includes `outstanding`: a submission the submitting thread
+    // launched itself leaves the queues empty but still has to be reaped.
     if (Clock::now() - last_work <
         std::chrono::microseconds(c->cfg.serve_spin_us)) {
       std::this_thread::yield();
@@ -630,7 +638,8 @@ void scheduler_main(ms_ctx* c) {
     }
     std::unique_lock<std::mutex> lk(c->q_mu);
     c->q_cv.wait_for(lk, std::chrono::milliseconds(2), [c] {
-      return c->stop.load() || !c->demand_q.empty() || !c->prefetch_q.empty();
+      return c->stop.load() || c->outstanding.load() != 0 ||
+             !c->demand_q.empty() || !c->prefetch_q.empty();
     });
   }
 }
