@@ -800,9 +800,9 @@ def main():
     ap.add_argument("--predictor-steps", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the page cipher needs no "
-              "cross-GPU step, and this build runs on a single MI355X; "
-              "use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: pages are independent, so the "
+              "cipher needs no cross-GPU step and N GPUs would each run this "
+              "figure on their own share; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -69,7 +69,7 @@ typedef enum ms_status {
     MS_EDEVICE = -6,     /* the GPU or the HIP runtime reported an error */
     MS_ECLOSED = -7,     /* context is shutting down */
     MS_ETIMEDOUT = -8,   /* ms_poll timed out with requests pending */
-    MS_ENOTSUP = -9,     /* option not supported by this build */
+    MS_ENOTSUP = -9,     /* option not supported by this entry point */
     MS_ECANCELED = -10   /* request cancelled (client cancelled or dropped) */
 } ms_status;
 
