@@ -106,7 +106,12 @@ ms_status ms_resident_submit(ms_resident *r, const void *src, void *dst,
  * a linear nonce.  src and dst are each pinned host memory or device memory
  * of the context's GPU, 16-byte aligned, src == dst or not overlapping.  The
  * request becomes ceil(n_pages / desc_pages) descriptors, queued together or
- * not at all; the ticket covers all of them.  Never blocks.  Errors:
+ * not at all; the ticket covers all of them.  Never blocks.  The kernel
+ * does not wait for any stream: the source bytes must be complete when this
+ * is called (synchronize the stream that produced them), and nothing may
+ * read or write the destination until ms_resident_poll reports the ticket
+ * done; from then on the pages are visible to the host and to later device
+ * work.  Errors:
  * MS_EINVAL (a key index the engine does not hold, pageable or managed
  * memory, another GPU's memory, or more descriptors than the ring holds),
  * MS_ENOTSUP (array nonces), MS_EAGAIN (ring full now), MS_ECLOSED (the
