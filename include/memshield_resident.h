@@ -16,13 +16,14 @@
  *     scalar registers; the host copy is wiped as soon as it is on the GPU;
  *   - ms_resident_submit writes 64-byte descriptors (up to desc_pages pages
  *     each) into a ring in pinned host memory; any number of host threads may
- *     submit; the kernel's workers take descriptors in ring order;
+ *     submit; each worker serves its own fixed share of the ring positions;
  *   - pages are in pinned, coherent host memory (ms_host_alloc of
  *     memshield_host.h, or hipHostMalloc with hipHostMallocCoherent), which
  *     is the paper's data path, or in device memory of the context's GPU
  *     (a page request then never waits for a kernel launch); the kernel
  *     reads and writes them while it runs; nonces follow the linear rule
- *     (virtual address, PID) of ms_nonce, which is the paper's;
+ *     (virtual address, PID) of ms_nonce, which is the paper's, or come from
+ *     an array of 12-byte nonces in device or pinned host memory;
  *   - an engine holds one key (the paper's design: it stays in every
  *     worker's registers) or, started with ms_resident_start_keys, up to
  *     MS_RESIDENT_MAX_KEYS keys taken from the context's key table (one per
@@ -94,7 +95,7 @@ ms_status ms_resident_start_keys(ms_ctx *ctx, const ms_resident_config *cfg,
                                  ms_resident **out);
 
 /*
- * Queue n_pages pages from src to dst with key index 0 and a linear nonce;
+ * Queue n_pages pages from src to dst with key index 0;
  * ms_resident_submit_keyed with key_index 0.
  */
 ms_status ms_resident_submit(ms_resident *r, const void *src, void *dst,
@@ -103,7 +104,9 @@ ms_status ms_resident_submit(ms_resident *r, const void *src, void *dst,
 
 /*
  * Queue n_pages pages from src to dst with the engine's key `key_index` and
- * a linear nonce.  src and dst are each pinned host memory or device memory
+ * a linear nonce, or an array of n_pages 12-byte nonces (device memory of
+ * the context's GPU or pinned host memory, 4-byte aligned; it must stay
+ * unchanged until the ticket is done).  src and dst are each pinned host memory or device memory
  * of the context's GPU, 16-byte aligned, src == dst or not overlapping.  The
  * request becomes ceil(n_pages / desc_pages) descriptors, queued together or
  * not at all; the ticket covers all of them.  Never blocks.  The kernel
@@ -114,7 +117,7 @@ ms_status ms_resident_submit(ms_resident *r, const void *src, void *dst,
  * work.  Errors:
  * MS_EINVAL (a key index the engine does not hold, pageable or managed
  * memory, another GPU's memory, or more descriptors than the ring holds),
- * MS_ENOTSUP (array nonces), MS_EAGAIN (ring full now), MS_ECLOSED (the
+ * MS_EAGAIN (ring full now), MS_ECLOSED (the
  * kernel has stopped), MS_EDEVICE (the kernel rejected a descriptor).
  * Thread-safe.
  */

@@ -12,18 +12,20 @@ constexpr uint32_t kRkMaxKeys = 64;
 
 // One descriptor of the host's submission ring: a run of pages (at most
 // max_pages) in pinned host memory or device memory, ciphered with one of
-// the resident keys and the linear nonce rule.  64 bytes, in pinned host
-// memory.
+// the resident keys and the linear rule or an array of nonces.  64 bytes,
+// in pinned host memory.
 struct RkDesc {
   uint64_t src;           // GPU-visible address of the first source page
   uint64_t dst;           // same for the destination
-  uint64_t nonce_base;    // nonce of page 0 (state words 13..14)
-  uint64_t nonce_stride;  // nonce increment per page
+  uint64_t nonce_base;    // kind 1: nonce of page 0 (state words 13..14);
+                          // kind 0: GPU-visible address of page 0's 12
+                          // nonce bytes (3 words per page follow)
+  uint64_t nonce_stride;  // kind 1: nonce increment per page
   uint64_t seq;           // ring position the descriptor was written for
   uint32_t n_pages;
-  uint32_t tag;           // state word 15
+  uint32_t tag;           // kind 1: state word 15
   uint32_t key;           // index into the engine's keys, < n_keys
-  uint32_t pad32;
+  uint32_t kind;          // 0 nonce array, 1 linear nonce (as ms_nonce)
   uint64_t pad;
 };
 static_assert(sizeof(RkDesc) == 64, "RkDesc layout");

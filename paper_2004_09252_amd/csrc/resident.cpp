@@ -490,14 +490,18 @@ ms_status ms_resident_submit_keyed(ms_resident* r, uint32_t key_index,
                                    ms_ticket* ticket_out) {
   if (!r || !nonce || n_pages == 0 || key_index >= r->n_keys)
     return MS_EINVAL;
-  if (nonce->kind == MS_NONCE_ARRAY) return MS_ENOTSUP;
-  if (nonce->kind != MS_NONCE_LINEAR) return MS_EINVAL;
+  if (nonce->kind != MS_NONCE_LINEAR && nonce->kind != MS_NONCE_ARRAY)
+    return MS_EINVAL;
   if (n_pages > UINT64_MAX / MS_PAGE_SIZE) return MS_EINVAL;
   const uint64_t bytes = n_pages * MS_PAGE_SIZE;
-  uint64_t s = 0, d = 0;
+  uint64_t s = 0, d = 0, na = 0;
   ms_status st = ms_internal_classify_any(r->ctx, src, bytes, 16, &s);
   if (st) return st;
   if ((st = ms_internal_classify_any(r->ctx, dst, bytes, 16, &d))) return st;
+  if (nonce->kind == MS_NONCE_ARRAY &&
+      (st = ms_internal_classify_any(r->ctx, nonce->array,
+                                     n_pages * MS_NONCE_BYTES, 4, &na)))
+    return st;
   const uintptr_t a = reinterpret_cast<uintptr_t>(src);
   const uintptr_t b = reinterpret_cast<uintptr_t>(dst);
   if (a != b && a < b + bytes && b < a + bytes) return MS_EINVAL;
@@ -519,10 +523,18 @@ ms_status ms_resident_submit_keyed(ms_resident* r, uint32_t key_index,
     ms::RkDesc& x = r->ring[q & (depth - 1)];
     x.src = s + first * MS_PAGE_SIZE;
     x.dst = d + first * MS_PAGE_SIZE;
-    x.nonce_base = nonce->base + first * nonce->stride;
-    x.nonce_stride = nonce->stride;
+    if (nonce->kind == MS_NONCE_ARRAY) {
+      x.nonce_base = na + first * MS_NONCE_BYTES;
+      x.nonce_stride = 0;
+      x.tag = 0;
+      x.kind = 0;
+    } else {
+      x.nonce_base = nonce->base + first * nonce->stride;
+      x.nonce_stride = nonce->stride;
+      x.tag = nonce->tag;
+      x.kind = 1;
+    }
     x.n_pages = (uint32_t)(n_pages - first < per ? n_pages - first : per);
-    x.tag = nonce->tag;
     x.key = key_index;
     x.seq = q;
   }

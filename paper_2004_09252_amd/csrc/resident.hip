@@ -119,11 +119,59 @@ __device__ void poll_host(const RkArgs& a, uint32_t lane) {
                      __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// Cipher n_pages consecutive pages from `src` to `dst` (GPU-visible
+// addresses) with key `kk`.  ARRAY: page p's nonce is the 12 bytes at nb +
+// 12p (every lane reads them); otherwise it is LE64(nb + p*ns) || tag.
+template <int ROUNDS, bool ARRAY>
+__device__ __forceinline__ void cipher_run(const uint32_t (&kk)[8],
+                                           uint64_t src, uint64_t dst,
+                                           uint64_t nb, uint64_t ns,
+                                           uint32_t tag, uint32_t n_pages,
+                                           uint4* lds, uint32_t lane) {
+  for (uint32_t p = 0; p < n_pages; ++p) {
+    const uint64_t s = src + (uint64_t)p * kPageBytes;
+    const uint64_t o = dst + (uint64_t)p * kPageBytes;
+    // the page's 512 8-byte units: access q of lane l is unit 64*q + l,
+    // issued before the keystream so the link latency overlaps the rounds
+    uint64_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = ld_page(s + 8u * (q * 64 + lane));
+    uint32_t n[3];
+    if (ARRAY) {
+      const uint32_t* na =
+          reinterpret_cast<const uint32_t*>(nb + (uint64_t)p * 12u);
+      n[0] = uni(ld_sys32(na));
+      n[1] = uni(ld_sys32(na + 1));
+      n[2] = uni(ld_sys32(na + 2));
+    } else {
+      const uint64_t nv = nb + (uint64_t)p * ns;
+      n[0] = (uint32_t)nv;
+      n[1] = (uint32_t)(nv >> 32);
+      n[2] = tag;
+    }
+    uint32_t ks[16];
+    keystream<ROUNDS>(ks, kk, n, lane);  // block `lane` = bytes 64*lane..
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      lds[lds_slot(lane * 4 + q)] =
+          make_uint4(ks[4 * q], ks[4 * q + 1], ks[4 * q + 2], ks[4 * q + 3]);
+    wave_lds_order();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const uint32_t unit = q * 64 + lane;  // bytes 8*unit .. 8*unit+7
+      const uint2 x = reinterpret_cast<const uint2*>(
+          &lds[lds_slot(unit >> 1)])[unit & 1];
+      st_page(o + 8u * unit, v[q] ^ (((uint64_t)x.y << 32) | x.x));
+    }
+    wave_lds_order();
+  }
+}
+
 // Cipher the pages of the descriptor at ring position `pos`, then mark the
 // position complete.  A descriptor that does not carry its own position, has
-// a page count outside 1..max_pages or a key index outside the engine's keys
-// is not touched and raises `error`.  `k` is the key of a one-key engine;
-// `keytab` the LDS key table of a many-key engine.
+// a page count outside 1..max_pages, a key index outside the engine's keys
+// or an unknown nonce kind is not touched and raises `error`.  `k` is the
+// key of a one-key engine; `keytab` the LDS key table of a many-key engine.
 template <int ROUNDS>
 __device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
                           const uint32_t* keytab, uint64_t pos, uint4* lds,
@@ -148,11 +196,13 @@ __device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
   const uint64_t ns = field(3);
   const uint64_t seq = field(4);
   const uint64_t pt = field(5);  // n_pages | tag << 32
-  const uint32_t key = (uint32_t)field(6);
+  const uint64_t kk64 = field(6);  // key | kind << 32
+  const uint32_t key = (uint32_t)kk64;
+  const uint32_t kind = (uint32_t)(kk64 >> 32);
   const uint32_t n_pages = (uint32_t)pt;
   const uint32_t tag = (uint32_t)(pt >> 32);
   if (seq != pos || n_pages == 0 || n_pages > a.max_pages ||
-      key >= a.n_keys) {
+      key >= a.n_keys || kind > 1) {
     st_sys32(&a.hctl->error, 1u);
   } else {
     uint32_t kk[8];
@@ -165,32 +215,11 @@ __device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) asm volatile("" : "+s"(kk[i]) : : "memory");
-    for (uint32_t p = 0; p < n_pages; ++p) {
-      const uint64_t s = src + (uint64_t)p * kPageBytes;
-      const uint64_t o = dst + (uint64_t)p * kPageBytes;
-      // the page's 512 8-byte units: access q of lane l is unit 64*q + l,
-      // issued before the keystream so the link latency overlaps the rounds
-      uint64_t v[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = ld_page(s + 8u * (q * 64 + lane));
-      const uint64_t nv = nb + (uint64_t)p * ns;
-      const uint32_t n[3] = {(uint32_t)nv, (uint32_t)(nv >> 32), tag};
-      uint32_t ks[16];
-      keystream<ROUNDS>(ks, kk, n, lane);  // block `lane` = bytes 64*lane..
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        lds[lds_slot(lane * 4 + q)] =
-            make_uint4(ks[4 * q], ks[4 * q + 1], ks[4 * q + 2], ks[4 * q + 3]);
-      wave_lds_order();
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const uint32_t unit = q * 64 + lane;  // bytes 8*unit .. 8*unit+7
-        const uint2 x = reinterpret_cast<const uint2*>(
-            &lds[lds_slot(unit >> 1)])[unit & 1];
-        st_page(o + 8u * unit, v[q] ^ (((uint64_t)x.y << 32) | x.x));
-      }
-      wave_lds_order();
-    }
+    // the nonce kind is decided once per descriptor, outside the page loop
+    if (kind == 0)
+      cipher_run<ROUNDS, true>(kk, src, dst, nb, ns, tag, n_pages, lds, lane);
+    else
+      cipher_run<ROUNDS, false>(kk, src, dst, nb, ns, tag, n_pages, lds, lane);
   }
   // The page stores are complete before the completion word is written.
   // Every global store of this worker since its last completion word is a

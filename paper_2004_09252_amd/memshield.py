@@ -590,7 +590,8 @@ def _nbytes(buf) -> int:
 class Resident:
     """A resident-key engine (include/memshield_resident.h) of an Engine.
     Pages are HostBuffers (pinned, coherent host memory) or device tensors;
-    nonces are linear; `key_index` picks one of the engine's keys."""
+    nonces are linear or an array; `key_index` picks one of the engine's
+    keys."""
 
     def __init__(self, engine, handle: int):
         self.engine, self.handle = engine, handle

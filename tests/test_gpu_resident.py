@@ -267,9 +267,13 @@ def test_rejections(ms, eng):
                                      lin)[0] == ms.MS_EINVAL
         assert ms.ms_resident_submit(h, host.ptr, host.ptr, 0,
                                      lin)[0] == ms.MS_EINVAL
-        arr = ms.ms_nonce(ms.MS_NONCE_ARRAY, 0, dev.data_ptr(), 0, 0)
+        # a nonce array in pageable memory, or not 4-byte aligned
+        arr = ms.ms_nonce(ms.MS_NONCE_ARRAY, 0, pageable.ctypes.data, 0, 0)
         assert ms.ms_resident_submit(h, host.ptr, host.ptr, 1,
-                                     arr)[0] == ms.MS_ENOTSUP
+                                     arr)[0] == ms.MS_EINVAL
+        arr = ms.ms_nonce(ms.MS_NONCE_ARRAY, 0, dev.data_ptr() + 2, 0, 0)
+        assert ms.ms_resident_submit(h, host.ptr, host.ptr, 1,
+                                     arr)[0] == ms.MS_EINVAL
         assert ms.ms_resident_poll(h, [12345 << 24 | 1])[0] == ms.MS_EINVAL
         t = r.submit(host, host, lin, n_pages=1)
         r.wait([t])
@@ -557,3 +561,41 @@ def test_device_pages_producers_small_ring(ms):
     finally:
         r.stop()
         eng.close()
+
+
+@pytest.mark.parametrize("where", ["device", "host"])
+def test_array_nonces_bit_exact(ms, eng, where):
+    """Nonces from an array of 12-byte values (in HBM with device pages, in
+    pinned host memory with host pages), as for the launch paths."""
+    _note("resident array nonces %s" % where)
+    import torch
+    rng = np.random.default_rng(75)
+    key_b = rng.bytes(32)
+    n = 37
+    data = workloads.random_pages(rng, n)
+    nonces = np.frombuffer(rng.bytes(12 * n), dtype=np.uint8).reshape(n, 12)
+    want = oracle.cipher_pages(key_b, nonces, data)
+    r = _start(eng, key_b, workers=64, desc_pages=4)
+    try:
+        if where == "device":
+            src = _dev(torch, data)
+            dst = torch.zeros_like(src)
+            arr = torch.from_numpy(nonces.reshape(-1).copy()).to("cuda")
+            torch.cuda.synchronize()
+            nonce = ms.ms_nonce(ms.MS_NONCE_ARRAY, 0, arr.data_ptr(), 0, 0)
+            r.wait([r.submit(src, dst, nonce)])
+            got = dst.cpu().numpy().reshape(n, 4096)
+        else:
+            src = eng.host_alloc(n * 4096)
+            dst = eng.host_alloc(n * 4096)
+            arr = eng.host_alloc(12 * n)
+            src.array[:] = data.reshape(-1)
+            arr.array[:] = nonces.reshape(-1)
+            nonce = ms.ms_nonce(ms.MS_NONCE_ARRAY, 0, arr.ptr, 0, 0)
+            r.wait([r.submit(src, dst, nonce)])
+            got = dst.array.reshape(n, 4096).copy()
+            for b in (src, dst, arr):
+                b.free()
+        assert np.array_equal(got, want)
+    finally:
+        r.stop()
