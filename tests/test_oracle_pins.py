@@ -85,6 +85,24 @@ def test_python_oracle_agrees_with_c_oracle():
             oracle.chacha_block(key, ctr, nonce)
 
 
+@pytest.mark.parametrize("rounds", [8, 12])
+def test_reduced_round_oracles_agree(rounds):
+    """ChaCha12 and ChaCha8 (the cipher variants) have no library
+    reference here: the C and the independent Python oracle must agree on
+    blocks and whole pages, and the round count must matter (each variant
+    differs from the others and from ChaCha20)."""
+    key, nonce = _rand(32), _rand(12)
+    page = _rand(4096)
+    c_out = oracle.cipher_pages(key, np.frombuffer(nonce, np.uint8),
+                                np.frombuffer(page, np.uint8), rounds=rounds)
+    assert chacha_py.cipher_page(key, nonce, page, rounds) == c_out.tobytes()
+    for ctr in (0, 9, 63):
+        assert chacha_py.block(key, ctr, nonce, rounds) == \
+            oracle.chacha_block(key, ctr, nonce, rounds)
+    outs = {r: oracle.chacha_block(key, 5, nonce, r) for r in (8, 12, 20)}
+    assert len(set(outs.values())) == 3
+
+
 def test_python_oracle_matches_openssl():
     key, nonce = _rand(32), _rand(12)
     assert chacha_py.block(key, 3, nonce) == \
