@@ -1,7 +1,7 @@
-// A CPU stand-in for the part of the HIP runtime API that the engine's host
-// code (engine.cpp) uses, so that its queues, admission, tickets and
-// scheduler can be built with g++ and run under ThreadSanitizer on a machine
-// without a GPU.  TEST INFRASTRUCTURE ONLY: nothing in the library includes
+// A CPU stand-in for the part of the HIP runtime API that the library's host
+// code (engine.cpp, host_pages.cpp, resident.cpp) uses, so that its queues,
+// admission, tickets, scheduler and resident-engine ring can be built with
+// g++ and run under ThreadSanitizer on a machine without a GPU.  TEST INFRASTRUCTURE ONLY: nothing in the library includes
 // it; tests/test_scheduler_tsan_cpu.py puts this directory first on the
 // include path of a separate host build.
 //
@@ -94,6 +94,10 @@ hipError_t hipGetDeviceCount(int* n);
 hipError_t hipSetDevice(int d);
 hipError_t hipGetDevice(int* d);
 hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int d);
+typedef enum hipDeviceAttribute_t {
+  hipDeviceAttributeWallClockRate = 1
+} hipDeviceAttribute_t;
+hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int d);
 hipError_t hipGetLastError();
 hipError_t hipDeviceSynchronize();
 
@@ -122,6 +126,7 @@ hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
 hipError_t hipEventQuery(hipEvent_t e);
 hipError_t hipEventSynchronize(hipEvent_t e);
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned flags);
 
 hipError_t hipGraphCreate(hipGraph_t* g, unsigned flags);
 hipError_t hipGraphDestroy(hipGraph_t g);

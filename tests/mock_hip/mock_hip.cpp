@@ -141,6 +141,12 @@ hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int d) {
   std::strcpy(p->gcnArchName, "gfx950-mock");
   p->multiProcessorCount = 256;
   p->totalGlobalMem = (size_t)1 << 34;
+  p->pciBusID = 0x42;  // the mock HSA agent carries the same address
+  return hipSuccess;
+}
+hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int d) {
+  if (d != 0 || a != hipDeviceAttributeWallClockRate) return hipErrorInvalidValue;
+  *v = 100000;  // kHz: a 100 MHz wall clock, as the GPU's
   return hipSuccess;
 }
 hipError_t hipGetLastError() { return hipSuccess; }
@@ -272,6 +278,14 @@ hipError_t hipEventQuery(hipEvent_t e) {
 }
 hipError_t hipEventSynchronize(hipEvent_t e) {
   while (hipEventQuery(e) != hipSuccess) std::this_thread::yield();
+  return hipSuccess;
+}
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
+  // the stream's later work waits until the event's recorded work has run
+  const uint64_t seq = e->recorded.load();
+  resolve(s)->push([e, seq] {
+    while (e->done.load() < seq) std::this_thread::yield();
+  });
   return hipSuccess;
 }
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {

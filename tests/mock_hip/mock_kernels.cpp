@@ -1,9 +1,8 @@
 // CPU versions of the page kernels' launch functions (ms_kernels.h) for the
 // mock HIP runtime: each launch becomes an operation on its stream that
 // ciphers the same pages with the same keys and nonces through the C
-// oracle (test infrastructure only).  Also stubs for the host-page and
-// resident-key parts of the library, which the scheduler test does not
-// build.
+// oracle (test infrastructure only).  Also weak stubs for the host-page and
+// resident-key parts of the library, for a build that leaves them out.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -140,11 +139,11 @@ hipError_t launch_fill_u32(uint32_t* dst, uint32_t value, uint64_t n_words,
 
 }  // namespace ms
 
-// The scheduler test builds no host-page path and no resident-key engine.
-HostPath* ms_internal_host_path_create() {
+// Used when host_pages.cpp and resident.cpp are not linked in.
+__attribute__((weak)) HostPath* ms_internal_host_path_create() {
   return reinterpret_cast<HostPath*>(new char[1]);
 }
-void ms_internal_host_path_destroy(HostPath* h) {
+__attribute__((weak)) void ms_internal_host_path_destroy(HostPath* h) {
   delete[] reinterpret_cast<char*>(h);
 }
-void ms_internal_resident_stop_all(ms_ctx*) {}
+__attribute__((weak)) void ms_internal_resident_stop_all(ms_ctx*) {}
