@@ -532,7 +532,9 @@ def linear_nonce(base: int, stride: int, tag: int) -> ms_nonce:
 
 
 def array_nonce(t: torch.Tensor) -> ms_nonce:
-    return ms_nonce(MS_NONCE_ARRAY, 0, t.data_ptr(), 0, 0)
+    n = ms_nonce(MS_NONCE_ARRAY, 0, t.data_ptr(), 0, 0)
+    n._keep = t   # the tensor outlives the nonce that points into it
+    return n
 
 
 def _stream_handle(stream) -> int | None:
@@ -546,10 +548,30 @@ def _stream_handle(stream) -> int | None:
 def request(key: int, src: torch.Tensor, dst: torch.Tensor, n_pages: int,
             nonce: ms_nonce, op: int = MS_ENCRYPT, client: int = 0,
             src_offset_pages: int = 0, dst_offset_pages: int = 0) -> ms_request:
-    return ms_request(op, client, key,
-                      src.data_ptr() + src_offset_pages * PAGE_SIZE,
-                      dst.data_ptr() + dst_offset_pages * PAGE_SIZE,
-                      n_pages, nonce, 0, 0)
+    """A request over tensors; it holds them (and the nonce, which may hold
+    an array tensor), so that an Engine can keep them alive while the
+    request is in flight."""
+    r = ms_request(op, client, key,
+                   src.data_ptr() + src_offset_pages * PAGE_SIZE,
+                   dst.data_ptr() + dst_offset_pages * PAGE_SIZE,
+                   n_pages, nonce, 0, 0)
+    r._keep = (src, dst, nonce)
+    return r
+
+
+def _hold(pending: dict, tickets, keeps) -> None:
+    """Remember what each submitted ticket's buffers are (see _release)."""
+    for t, k in zip(tickets, keeps):
+        if t and k is not None:
+            pending[t] = k
+
+
+def _release(pending: dict, tickets, done) -> None:
+    """Forget the buffers of tickets that poll reported finished."""
+    if pending:
+        for t, d in zip(tickets, done):
+            if d != 0:
+                pending.pop(t, None)
 
 
 class HostBuffer:
@@ -595,6 +617,10 @@ class Resident:
 
     def __init__(self, engine, handle: int):
         self.engine, self.handle = engine, handle
+        # ticket -> the buffers it reads and writes, held until poll reports
+        # it finished (or stop): the caching allocator must not hand them to
+        # another tensor while the kernel still uses them
+        self._pending = {}
 
     def submit(self, src, dst, nonce, n_pages=None, key_index=0) -> int:
         if n_pages is None:
@@ -602,10 +628,14 @@ class Resident:
         st, t = ms_resident_submit_keyed(self.handle, key_index, _addr(src),
                                          _addr(dst), n_pages, nonce)
         _check(st, "ms_resident_submit_keyed")
+        _hold(self._pending, [t], [(src, dst, nonce)])
         return t
 
     def poll(self, tickets, timeout_s: float = 0.0):
-        return ms_resident_poll(self.handle, tickets, int(timeout_s * 1e9))
+        st, done = ms_resident_poll(self.handle, tickets, int(timeout_s * 1e9))
+        if st == MS_OK or st == MS_ETIMEDOUT:
+            _release(self._pending, tickets, done)
+        return st, done
 
     def wait(self, tickets, timeout_s: float = 30.0):
         st, done = self.poll(tickets, timeout_s)
@@ -625,6 +655,7 @@ class Resident:
             if self.engine.ctx:
                 st = ms_resident_stop(self.handle)
             self.handle = 0
+            self._pending.clear()
             if self in self.engine._residents:
                 self.engine._residents.remove(self)
             _check(st, "ms_resident_stop")
@@ -653,6 +684,7 @@ class Engine:
                 raise TypeError("unknown config field %r" % k)
             setattr(cfg, k, v)
         self.device = device
+        self._pending = {}   # ticket -> buffers held while it is in flight
         self._residents = []
         self._host_buffers = weakref.WeakSet()
         st, self.ctx = ms_init(device, cfg)
@@ -663,8 +695,9 @@ class Engine:
         if self.ctx:
             for r in list(self._residents):
                 r.stop()
-            ms_shutdown(self.ctx)
+            ms_shutdown(self.ctx)   # drains: nothing is in flight after it
             self.ctx = None
+            self._pending.clear()
             for b in list(self._host_buffers):
                 b._invalidate()
 
@@ -758,20 +791,28 @@ class Engine:
                "ms_process_batch")
 
     def submit(self, reqs) -> list:
+        """Queue requests; those built by `request` keep their tensors alive
+        until poll reports them finished, or drain or close."""
         st, t = ms_submit(self.ctx, reqs)
         _check(st, "ms_submit")
+        _hold(self._pending, t, [getattr(r, "_keep", None) for r in reqs])
         return t
 
     def poll(self, tickets, timeout_s: float = 0.0):
-        return ms_poll(self.ctx, tickets, int(timeout_s * 1e9))
+        st, done = ms_poll(self.ctx, tickets, int(timeout_s * 1e9))
+        if st == MS_OK or st == MS_ETIMEDOUT:
+            _release(self._pending, tickets, done)
+        return st, done
 
     def prefetch_hint(self, reqs) -> list:
         st, t = ms_prefetch_hint(self.ctx, reqs)
         _check(st, "ms_prefetch_hint")
+        _hold(self._pending, t, [getattr(r, "_keep", None) for r in reqs])
         return t
 
     def drain(self, timeout_s: float = 60.0):
         _check(ms_drain(self.ctx, int(timeout_s * 1e9)), "ms_drain")
+        self._pending.clear()
 
     def autotune(self, n_pages: int) -> ms_tuning:
         st, t = ms_autotune(self.ctx, n_pages)

@@ -162,3 +162,35 @@ def test_cipher_kernels_are_not_optimised_away(tmp_path):
         rounds = 20 if "ILi20E" in name else (12 if "ILi12E" in name else 8)
         assert body.count("v_alignbit_b32") >= 16 * rounds - 40, name
         assert body.count("global_store_dwordx4") >= 4, name
+
+
+def test_requests_hold_their_tensors_until_reported_finished():
+    """An asynchronous request's tensors stay referenced while it is in
+    flight (the caching allocator must not reuse them under the kernel):
+    `request` and `array_nonce` carry them, and the Engine's table keeps
+    them per ticket until poll reports the ticket finished."""
+    import gc
+    import weakref
+
+    import torch
+    from paper_2004_09252_amd import memshield as ms
+    src = torch.zeros(4096, dtype=torch.uint8)
+    dst = torch.zeros(4096, dtype=torch.uint8)
+    arr = torch.zeros(12, dtype=torch.uint8)
+    refs = [weakref.ref(t) for t in (src, dst, arr)]
+    r = ms.request(1, src, dst, 1, ms.array_nonce(arr))
+    del src, dst, arr
+    gc.collect()
+    assert all(w() is not None for w in refs)
+    pending = {}
+    # ticket 0 is a dropped prefetch hint: nothing to hold
+    ms._hold(pending, [0, 11], [(1,), getattr(r, "_keep")])
+    del r
+    gc.collect()
+    assert list(pending) == [11] and all(w() is not None for w in refs)
+    pending[12] = (2,)
+    ms._release(pending, [11, 12], [0, 1])   # 11 still running
+    assert list(pending) == [11]
+    ms._release(pending, [11], [ms.MS_ECANCELED])
+    gc.collect()
+    assert not pending and all(w() is None for w in refs)

@@ -599,3 +599,35 @@ def test_array_nonces_bit_exact(ms, eng, where):
         assert np.array_equal(got, want)
     finally:
         r.stop()
+
+
+def test_resident_holds_tensors_of_requests_in_flight(ms, eng):
+    """Device tensors given to the ring stay alive while their ticket is in
+    flight even when the caller drops them; poll reporting the ticket
+    finished releases them."""
+    _note("resident tensors held while in flight")
+    import gc
+    import weakref
+
+    import torch
+    rng = np.random.default_rng(77)
+    key_b = rng.bytes(32)
+    data = workloads.random_pages(rng, 40)
+    src = torch.from_numpy(data.reshape(-1)).to("cuda")
+    dst = torch.zeros_like(src)
+    torch.cuda.synchronize()
+    refs = [weakref.ref(src), weakref.ref(dst)]
+    r = _start(eng, key_b, workers=64, desc_pages=4)
+    try:
+        t = r.submit(src, dst, ms.linear_nonce(BASE, STRIDE, TAG))
+        out = dst  # one tensor kept to check the bytes
+        del src, dst
+        gc.collect()
+        assert all(w() is not None for w in refs)
+        r.wait([t])
+        gc.collect()
+        assert refs[0]() is None
+        assert np.array_equal(out.cpu().numpy().reshape(40, 4096),
+                              _want(key_b, data))
+    finally:
+        r.stop()

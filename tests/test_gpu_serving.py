@@ -343,3 +343,32 @@ def test_large_submitted_request_every_tiling(ms, tiling):
     finally:
         ms.ms_set_tuning(eng.ctx, None)
         eng.close()
+
+
+def test_engine_holds_tensors_of_requests_in_flight(ms):
+    """A request's tensors stay alive while it is in flight even when the
+    caller drops them, and are released once poll reports it finished."""
+    _note("tensors held while in flight")
+    import gc
+    import weakref
+
+    import torch
+    eng = ms.Engine(0)
+    try:
+        key = eng.key_generate()
+        src = torch.randint(0, 256, (256 * 4096,), dtype=torch.uint8,
+                            device="cuda")
+        dst = torch.zeros_like(src)
+        arr = torch.zeros(256 * 12, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        refs = [weakref.ref(t) for t in (src, dst, arr)]
+        t = eng.submit([ms.request(key, src, dst, 256, ms.array_nonce(arr))])
+        del src, dst, arr
+        gc.collect()
+        assert all(w() is not None for w in refs)
+        st, done = eng.poll(t, timeout_s=30)
+        assert st == 0 and done == [1]
+        gc.collect()
+        assert all(w() is None for w in refs)
+    finally:
+        eng.close()
