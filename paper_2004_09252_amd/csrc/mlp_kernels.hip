@@ -22,6 +22,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "memshield_mlp.h"
 
 namespace {
@@ -53,7 +55,25 @@ struct GemmArgs {
   int M, N, K;
   int lda, ldb, ldm, ldo, ldh;
   int transA, transB, relu;
+  // split K: blockIdx.z takes k in [z * k_split, (z + 1) * k_split); with
+  // splits > 1 each slice stores its float32 partial product in `part`
+  // (splits x M x N) and gemm_reduce_kernel adds the slices in order and
+  // applies the epilogue
+  float* part;
+  int splits, k_split;
 };
+
+// A GEMM with fewer output tiles than this, and a K of at least twice
+// kSplitMinK, splits K over up to kSplitMax workgroups per tile.
+constexpr int kSplitMaxTiles = 128;
+constexpr int kSplitMax = 4;
+constexpr int kSplitMinK = 256;
+constexpr uint64_t kSplitPartFloats =
+    (uint64_t)kSplitMax * kSplitMaxTiles * kTile * kTile;
+
+// The epilogue: bias, ReLU, mask, then the float32 and/or bf16 output.
+__device__ __forceinline__ void gemm_store(const GemmArgs& g, int row, int col,
+                                           float v);
 
 // Eight consecutive bf16 of a row starting at p, of which `valid` (0..8)
 // lie inside the matrix (the rest read as zero): one 16-byte load when all
@@ -192,12 +212,17 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
 
-  fetch(0);
-  for (int k0 = 0; k0 < g.K; k0 += kTileK) {
+  // this workgroup's K slice (the whole K unless split); k_split is a
+  // multiple of kTileK, so only the last slice can end inside a K step, and
+  // the loads mask that step against K
+  const int kbeg = blockIdx.z * g.k_split;
+  const int kend = min(g.K, kbeg + g.k_split);
+  fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += kTileK) {
     stash();
     lds_barrier();
     // the next step's global loads are in flight during this step's MFMAs
-    if (k0 + kTileK < g.K) fetch(k0 + kTileK);
+    if (k0 + kTileK < kend) fetch(k0 + kTileK);
 #pragma unroll
     for (int kk = 0; kk < kTileK; kk += 16) {
       const int kb = kk + 4 * (lane >> 4);
@@ -229,13 +254,32 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
         const int row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
         const int col = n0 + wn * 32 + j * 16 + (lane & 15);
         if (row >= g.M || col >= g.N) continue;
-        float v = acc[i][j][r];
-        if (g.bias) v += bf2f(g.bias[col]);
-        if (g.relu) v = v > 0.f ? v : 0.f;
-        if (g.mask && !(bf2f(g.mask[(size_t)row * g.ldm + col]) > 0.f)) v = 0.f;
-        if (g.outF) g.outF[(size_t)row * g.ldo + col] = v;
-        if (g.outH) g.outH[(size_t)row * g.ldh + col] = f2bf(v);
+        if (g.splits > 1)
+          g.part[((size_t)blockIdx.z * g.M + row) * g.N + col] = acc[i][j][r];
+        else
+          gemm_store(g, row, col, acc[i][j][r]);
       }
+}
+
+__device__ __forceinline__ void gemm_store(const GemmArgs& g, int row, int col,
+                                           float v) {
+  if (g.bias) v += bf2f(g.bias[col]);
+  if (g.relu) v = v > 0.f ? v : 0.f;
+  if (g.mask && !(bf2f(g.mask[(size_t)row * g.ldm + col]) > 0.f)) v = 0.f;
+  if (g.outF) g.outF[(size_t)row * g.ldo + col] = v;
+  if (g.outH) g.outH[(size_t)row * g.ldh + col] = f2bf(v);
+}
+
+// The K slices of a split GEMM added in slice order (so the sum does not
+// depend on which slice finished first), then the epilogue.
+__global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmArgs g) {
+  const size_t mn = (size_t)g.M * g.N;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < mn;
+       i += (size_t)gridDim.x * blockDim.x) {
+    float v = g.part[i];
+    for (int z = 1; z < g.splits; ++z) v += g.part[z * mn + i];
+    gemm_store(g, (int)(i / g.N), (int)(i % g.N), v);
+  }
 }
 
 // x[b][s*D + d] = E[ids[b][s]][d]; ids outside [0, V) are clamped.
@@ -529,7 +573,7 @@ bool shape_ok(const ms_mlp_shape* s) {
 
 struct Ws {
   uint16_t *x, *h1, *h2, *dlH, *dz2H, *dz1H;
-  float *logits, *dlF, *dz2F, *dz1F, *dxF, *row_loss, *colpart;
+  float *logits, *dlF, *dz2F, *dz1F, *dxF, *row_loss, *colpart, *part;
   uint64_t bytes;
 };
 
@@ -556,6 +600,7 @@ Ws carve(const ms_mlp_shape* s, int64_t Bm, uint8_t* base) {
   w.dxF = (float*)take(Bm * CD * 4);
   w.row_loss = (float*)take(Bm * 4);
   w.colpart = (float*)take((uint64_t)kColsumMaxSlices * (V > H ? V : H) * 4);
+  w.part = (float*)take(kSplitPartFloats * 4);
   w.bytes = off;
   return w;
 }
@@ -574,9 +619,29 @@ hipError_t colsum(const float* in, int M, int N, int ld, float* out,
   return hipGetLastError();
 }
 
-hipError_t gemm(const GemmArgs& g, hipStream_t s) {
-  dim3 grid((g.N + kTile - 1) / kTile, (g.M + kTile - 1) / kTile);
-  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, g);
+// Launch one GEMM; one with few output tiles and a long K is split over K
+// into the workspace's partial buffer, then reduced.
+hipError_t gemm(GemmArgs g, const Ws& w, hipStream_t s) {
+  const int tn = (g.N + kTile - 1) / kTile, tm = (g.M + kTile - 1) / kTile;
+  const int tiles = tn * tm;
+  int splits = 1;
+  if (tiles < kSplitMaxTiles) splits = std::min(kSplitMax, g.K / kSplitMinK);
+  g.k_split = g.K;
+  if (splits > 1) {
+    // slices of whole K steps; rounding up can leave fewer slices
+    g.k_split = ((g.K + splits - 1) / splits + kTileK - 1) / kTileK * kTileK;
+    splits = (g.K + g.k_split - 1) / g.k_split;
+  }
+  g.splits = splits > 1 ? splits : 1;
+  // splits * M * N <= kSplitMax * tiles * kTile^2 < kSplitPartFloats
+  g.part = w.part;
+  hipLaunchKernelGGL(gemm_bf16_kernel, dim3(tn, tm, g.splits), dim3(256), 0,
+                     s, g);
+  if (g.splits == 1) return hipGetLastError();
+  const uint64_t mn = (uint64_t)g.M * g.N;
+  hipLaunchKernelGGL(gemm_reduce_kernel,
+                     dim3((unsigned)std::min<uint64_t>((mn + 255) / 256, 1024)),
+                     dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
@@ -607,13 +672,13 @@ hipError_t forward_impl(const ms_mlp_shape* s, const uint16_t* P,
   if (e != hipSuccess) return e;
   GemmArgs g = gemm_args(w.x, CD, 0, P + off[1], H, 0, B, H, CD);
   g.bias = P + off[2]; g.relu = 1; g.outH = w.h1; g.ldh = H;
-  if ((e = gemm(g, st)) != hipSuccess) return e;
+  if ((e = gemm(g, w, st)) != hipSuccess) return e;
   g = gemm_args(w.h1, H, 0, P + off[3], H, 0, B, H, H);
   g.bias = P + off[4]; g.relu = 1; g.outH = w.h2; g.ldh = H;
-  if ((e = gemm(g, st)) != hipSuccess) return e;
+  if ((e = gemm(g, w, st)) != hipSuccess) return e;
   g = gemm_args(w.h2, H, 0, P + off[5], V, 0, B, V, H);
   g.bias = P + off[6]; g.outF = logits; g.ldo = V;
-  return gemm(g, st);
+  return gemm(g, w, st);
 }
 
 }  // namespace
@@ -673,32 +738,32 @@ ms_status ms_mlp_backward(const ms_mlp_shape* s, const uint16_t* P,
   // output layer: dW3 = h2^T dl, db3 = colsum(dl), dz2 = (dl W3^T) * (h2>0)
   GemmArgs g = gemm_args(w.h2, H, 1, w.dlH, V, 0, H, V, B);
   g.outF = G + off[5]; g.ldo = V;
-  if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
+  if (gemm(g, w, st) != hipSuccess) return MS_EDEVICE;
   if (colsum(w.dlF, B, V, V, G + off[6], w.colpart, st) != hipSuccess)
     return MS_EDEVICE;
   g = gemm_args(w.dlH, V, 0, P + off[5], V, 1, B, H, V);
   g.mask = w.h2; g.ldm = H; g.outF = w.dz2F; g.ldo = H; g.outH = w.dz2H;
   g.ldh = H;
-  if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
+  if (gemm(g, w, st) != hipSuccess) return MS_EDEVICE;
   // layer 2: dW2 = h1^T dz2, db2 = colsum(dz2), dz1 = (dz2 W2^T) * (h1>0)
   g = gemm_args(w.h1, H, 1, w.dz2H, H, 0, H, H, B);
   g.outF = G + off[3]; g.ldo = H;
-  if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
+  if (gemm(g, w, st) != hipSuccess) return MS_EDEVICE;
   if (colsum(w.dz2F, B, H, H, G + off[4], w.colpart, st) != hipSuccess)
     return MS_EDEVICE;
   g = gemm_args(w.dz2H, H, 0, P + off[3], H, 1, B, H, H);
   g.mask = w.h1; g.ldm = H; g.outF = w.dz1F; g.ldo = H; g.outH = w.dz1H;
   g.ldh = H;
-  if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
+  if (gemm(g, w, st) != hipSuccess) return MS_EDEVICE;
   // layer 1: dW1 = x^T dz1, db1 = colsum(dz1), dx = dz1 W1^T
   g = gemm_args(w.x, CD, 1, w.dz1H, H, 0, CD, H, B);
   g.outF = G + off[1]; g.ldo = H;
-  if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
+  if (gemm(g, w, st) != hipSuccess) return MS_EDEVICE;
   if (colsum(w.dz1F, B, H, H, G + off[2], w.colpart, st) != hipSuccess)
     return MS_EDEVICE;
   g = gemm_args(w.dz1H, H, 0, P + off[1], H, 1, B, CD, H);
   g.outF = w.dxF; g.ldo = CD;
-  if (gemm(g, st) != hipSuccess) return MS_EDEVICE;
+  if (gemm(g, w, st) != hipSuccess) return MS_EDEVICE;
   hipLaunchKernelGGL(embed_scatter_kernel, dim3(V), dim3(64), 0, st, w.dxF,
                      ids, B, s->context, s->embed, V, G + off[0]);
   return hipGetLastError() == hipSuccess ? MS_OK : MS_EDEVICE;
