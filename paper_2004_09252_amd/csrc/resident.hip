@@ -34,9 +34,9 @@
 //     (coalesced 8-byte columns, no stale cached copy is possible, whether a
 //     page is in host memory or in HBM), XORs the
 //     keystream, transposed through LDS as in the launch-per-call kernels,
-//     writes the pages back with system-scope stores, and after a release
-//     fence writes the position into the slot's completion word, which the
-//     host polls;
+//     writes the pages back with system-scope stores, and once those stores
+//     are acknowledged writes the position into the slot's completion word,
+//     which the host polls;
 //   * every wait is bounded: the poller leaves when the host sets `stop` or
 //     after `idle_ticks` without host activity, and the workers leave when
 //     the poller does, so the launch always drains;
@@ -96,12 +96,19 @@ __device__ void poll_host(const RkArgs& a, uint32_t lane) {
   uint64_t last_pub = 0, last_hb = 0;
   uint64_t t_last = wall_clock64();
   for (;;) {
-    if (uni(ld_sys32(&a.hctl->stop))) break;
+    // the three control words in one round trip over the link
+    const uint32_t stop = ld_sys32(&a.hctl->stop);
     const uint64_t pub = uni64(ld_sys64(&a.hctl->published));
     const uint64_t hb = uni64(ld_sys64(&a.hctl->heartbeat));
+    if (uni(stop)) break;
     const uint64_t now = wall_clock64();
     if (pub != last_pub) {
-      __hip_atomic_store(&a.dctl->published, pub, __ATOMIC_RELEASE,
+      // A relaxed store: the count orders nothing this wave wrote.  The
+      // descriptors it covers were written by the host before the host's
+      // count, and a worker reads them with system-scope loads only after it
+      // sees this count, so they reach it whole.  (A release here would
+      // write back the L2 at every new count.)
+      __hip_atomic_store(&a.dctl->published, pub, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
       last_pub = pub;
       t_last = now;
