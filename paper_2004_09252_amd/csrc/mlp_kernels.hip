@@ -495,24 +495,23 @@ __device__ __forceinline__ bool ranks_before(float av, int ai, float bv,
   return av > bv || (av == bv && ai < bi);
 }
 
+// Values a lane loads at once: the loads of a chunk are independent, so
+// the row costs one memory round trip per chunk instead of one per value.
+constexpr int kTopkChunk = 16;
+
 __global__ __launch_bounds__(64) void topk_kernel(
     const float* __restrict__ logits, int V, int k, int exclude,
     int32_t* __restrict__ out, float* __restrict__ prob) {
   const int b = blockIdx.x;
   const int lane = threadIdx.x;
   const float* row = logits + (int64_t)b * V;
+  // This lane's running maximum and sum of exp(x - max) over its positions
+  // (one pass; the lanes' sums are rescaled to the row maximum at the end).
   float mx = -INFINITY, sum = 0.f;
-  if (prob) {
-    for (int i = lane; i < V; i += 64) mx = fmaxf(mx, row[i]);
-    for (int off = 32; off > 0; off >>= 1)
-      mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-    for (int i = lane; i < V; i += 64) sum += expf(row[i] - mx);
-    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
-  }
-  // One pass over the row: each lane keeps the best 16 of its positions
-  // lane, lane + 64, ... (NaN counts as -inf, `exclude` is skipped) sorted
-  // in registers; an entry enters by swapping down the list.  The best k
-  // of the row are the best k of the lanes' lists.
+  // Each lane keeps the best 16 of its positions lane, lane + 64, ...
+  // (NaN counts as -inf, `exclude` and positions past the row are left out)
+  // sorted in registers; an entry enters by swapping down the list.  The
+  // best k of the row are the best k of the lanes' lists.
   float lv[16];
   int li[16];
 #pragma unroll
@@ -520,21 +519,54 @@ __global__ __launch_bounds__(64) void topk_kernel(
     lv[t] = -INFINITY;
     li[t] = 0x7fffffff;
   }
-  for (int i = lane; i < V; i += 64) {
-    if (i == exclude) continue;
-    float cv = row[i];
-    if (cv != cv) cv = -INFINITY;
-    int ci = i;
+  for (int base = 0; base < V; base += 64 * kTopkChunk) {
+    float x[kTopkChunk];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const bool before = ranks_before(cv, ci, lv[t], li[t]);
-      const float tv = lv[t];
-      const int ti = li[t];
-      lv[t] = before ? cv : tv;
-      li[t] = before ? ci : ti;
-      cv = before ? tv : cv;
-      ci = before ? ti : ci;
+    for (int t = 0; t < kTopkChunk; ++t) {
+      const int i = base + 64 * t + lane;
+      x[t] = i < V ? row[i] : -INFINITY;
     }
+    if (prob) {
+      float m = mx;
+#pragma unroll
+      for (int t = 0; t < kTopkChunk; ++t) m = fmaxf(m, x[t]);
+      if (m != -INFINITY) {
+        float s2 = sum * expf(mx - m);
+#pragma unroll
+        for (int t = 0; t < kTopkChunk; ++t) s2 += expf(x[t] - m);
+        sum = s2;
+        mx = m;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kTopkChunk; ++t) {
+      const int i = base + 64 * t + lane;
+      // a left-out position becomes (-inf, INT_MAX), which never ranks
+      // before an entry of the list (the list starts full of those)
+      const bool in = i < V && i != exclude;
+      float cv = in ? (x[t] != x[t] ? -INFINITY : x[t]) : -INFINITY;
+      int ci = in ? i : 0x7fffffff;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const bool before = ranks_before(cv, ci, lv[u], li[u]);
+        const float tv = lv[u];
+        const int ti = li[u];
+        lv[u] = before ? cv : tv;
+        li[u] = before ? ci : ti;
+        cv = before ? tv : cv;
+        ci = before ? ti : ci;
+      }
+    }
+  }
+  if (prob) {
+    // the row maximum, then each lane's sum rescaled to it
+    float rm = mx;
+    for (int off = 32; off > 0; off >>= 1)
+      rm = fmaxf(rm, __shfl_xor(rm, off, 64));
+    float rs = mx == -INFINITY ? 0.f : sum * expf(mx - rm);
+    for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off, 64);
+    mx = rm;
+    sum = rs;
   }
   // k rounds: the best list head over the wave, popped by its lane
   for (int r = 0; r < k; ++r) {

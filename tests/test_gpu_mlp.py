@@ -200,3 +200,46 @@ def test_ragged_split_k_matches_reference_and_repeats_exactly():
         _close(gg[k].numpy(), g[k], "grad " + k)
     pred.backward(ids, tgt)
     assert np.array_equal(pred.grads.cpu().numpy(), first.numpy())
+
+
+def test_topk_ragged_vocab_over_several_chunks():
+    """A vocabulary of 2500 (three 1024-wide chunks, the last ragged), an
+    excluded id, a row that is -inf but for one value, ties, and rows with
+    NaN (ranked as -inf): ids equal the reference's exactly, probabilities
+    the float64 softmax within 1e-5."""
+    _note("topk V=2500")
+    import torch
+    from paper_2004_09252_amd import memshield as ms
+    rng = np.random.default_rng(31)
+    B, V, k, exclude = 37, 2500, 16, 1234
+    host = rng.normal(0, 3, (B, V)).astype(np.float32)
+    host[0, :] = -np.inf
+    host[0, 2499] = 1.0
+    host[1] = np.floor(host[1])           # ties within and across lanes
+    host[2, 2040:2060] = host[2].max() + 1.0   # ties across a chunk edge
+    host[3, exclude] = host[3].max() + 5.0     # the best is excluded
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def run(h, with_prob):
+        logits = torch.from_numpy(h).to("cuda")
+        ids = torch.empty(B * k, dtype=torch.int32, device="cuda")
+        pr = torch.empty(B * k, dtype=torch.float32, device="cuda")
+        st = ms.ms_mlp_topk(logits.data_ptr(), B, V, k, exclude,
+                            ids.data_ptr(),
+                            pr.data_ptr() if with_prob else None, stream)
+        assert st == ms.MS_OK
+        torch.cuda.synchronize()
+        return ids.view(B, k).cpu().numpy(), pr.view(B, k).cpu().numpy()
+
+    got, prob = run(host, True)
+    want = mlp_ref.topk_ids(host, k, exclude=exclude)
+    assert np.array_equal(got, want)
+    h64 = host.astype(np.float64)
+    sm = np.exp(h64 - h64.max(axis=1, keepdims=True))
+    sm /= sm.sum(axis=1, keepdims=True)
+    assert np.max(np.abs(prob - np.take_along_axis(sm, want, axis=1))) < 1e-5
+    nan = host.copy()
+    nan[5:9, ::7] = np.nan
+    got, _ = run(nan, False)
+    ranked = np.where(np.isnan(nan), -np.inf, nan)
+    assert np.array_equal(got, mlp_ref.topk_ids(ranked, k, exclude=exclude))
