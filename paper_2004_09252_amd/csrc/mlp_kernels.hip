@@ -24,6 +24,7 @@
 
 #include <algorithm>
 
+#include "gemm_split.h"
 #include "memshield_mlp.h"
 
 namespace {
@@ -31,8 +32,8 @@ namespace {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kTile = 64;
-constexpr int kTileK = 128;
+constexpr int kTile = ms::kGemmTile;
+constexpr int kTileK = ms::kGemmTileK;
 
 __device__ __forceinline__ float bf2f(uint16_t h) {
   return __uint_as_float((uint32_t)h << 16);
@@ -63,13 +64,8 @@ struct GemmArgs {
   int splits, k_split;
 };
 
-// A GEMM with fewer output tiles than this, and a K of at least twice
-// kSplitMinK, splits K over up to kSplitMax workgroups per tile.
-constexpr int kSplitMaxTiles = 128;
-constexpr int kSplitMax = 4;
-constexpr int kSplitMinK = 256;
-constexpr uint64_t kSplitPartFloats =
-    (uint64_t)kSplitMax * kSplitMaxTiles * kTile * kTile;
+// the split plan and the partial buffer's size (gemm_split.h)
+using ms::kSplitPartFloats;
 
 // The epilogue: bias, ReLU, mask, then the float32 and/or bf16 output.
 __device__ __forceinline__ void gemm_store(const GemmArgs& g, int row, int col,
@@ -655,17 +651,10 @@ hipError_t colsum(const float* in, int M, int N, int ld, float* out,
 // into the workspace's partial buffer, then reduced.
 hipError_t gemm(GemmArgs g, const Ws& w, hipStream_t s) {
   const int tn = (g.N + kTile - 1) / kTile, tm = (g.M + kTile - 1) / kTile;
-  const int tiles = tn * tm;
-  int splits = 1;
-  if (tiles < kSplitMaxTiles) splits = std::min(kSplitMax, g.K / kSplitMinK);
-  g.k_split = g.K;
-  if (splits > 1) {
-    // slices of whole K steps; rounding up can leave fewer slices
-    g.k_split = ((g.K + splits - 1) / splits + kTileK - 1) / kTileK * kTileK;
-    splits = (g.K + g.k_split - 1) / g.k_split;
-  }
-  g.splits = splits > 1 ? splits : 1;
-  // splits * M * N <= kSplitMax * tiles * kTile^2 < kSplitPartFloats
+  // splits * M * N <= kSplitPartFloats (tests/test_gemm_split_cpu.py)
+  const ms::SplitPlan plan = ms::split_plan(g.M, g.N, g.K);
+  g.splits = plan.splits;
+  g.k_split = plan.k_split;
   g.part = w.part;
   hipLaunchKernelGGL(gemm_bf16_kernel, dim3(tn, tm, g.splits), dim3(256), 0,
                      s, g);
