@@ -238,8 +238,9 @@ ms_status check_request(ms_ctx* c, const ms_request& r, uint32_t* slot,
     const uint64_t bytes = r.n_pages * MS_PAGE_SIZE;
     ms_status st = check_device_range(c, r.src, bytes, 16);
     if (st) return st;
-    st = check_device_range(c, r.dst, bytes, 16);
-    if (st) return st;
+    // in place: the same range, already checked
+    if (r.dst != r.src && (st = check_device_range(c, r.dst, bytes, 16)))
+      return st;
     const uintptr_t s = reinterpret_cast<uintptr_t>(r.src);
     const uintptr_t d = reinterpret_cast<uintptr_t>(r.dst);
     if (s != d && ranges_overlap(s, bytes, d, bytes)) return MS_EINVAL;

@@ -245,7 +245,11 @@ ms_status host_call(ms_ctx* c, ms_key key, const void* src, void* dst,
   const uint64_t bytes = n_pages * MS_PAGE_SIZE;
   Buf s{}, d{};
   if ((st = classify(c, src, bytes, 16, &s))) return st;
-  if ((st = classify(c, dst, bytes, 16, &d))) return st;
+  // in place: the same range, already classified
+  if (dst == src)
+    d = s;
+  else if ((st = classify(c, dst, bytes, 16, &d)))
+    return st;
   const uintptr_t a = reinterpret_cast<uintptr_t>(src);
   const uintptr_t b = reinterpret_cast<uintptr_t>(dst);
   if (a != b && a < b + bytes && b < a + bytes) return MS_EINVAL;

@@ -497,7 +497,11 @@ ms_status ms_resident_submit_keyed(ms_resident* r, uint32_t key_index,
   uint64_t s = 0, d = 0, na = 0;
   ms_status st = ms_internal_classify_any(r->ctx, src, bytes, 16, &s);
   if (st) return st;
-  if ((st = ms_internal_classify_any(r->ctx, dst, bytes, 16, &d))) return st;
+  // in place: the same range, already classified
+  if (dst == src)
+    d = s;
+  else if ((st = ms_internal_classify_any(r->ctx, dst, bytes, 16, &d)))
+    return st;
   if (nonce->kind == MS_NONCE_ARRAY &&
       (st = ms_internal_classify_any(r->ctx, nonce->array,
                                      n_pages * MS_NONCE_BYTES, 4, &na)))
