@@ -655,11 +655,18 @@ class Resident:
             if self.engine.ctx:
                 st = ms_resident_stop(self.handle)
             self.handle = 0
-            self._pending.clear()
+            if st != MS_OK:
+                # the kernel did not stop, and the library keeps every buffer
+                # it could still touch: keep the tensors alive with them
+                _never_freed.append(self._pending)
+            self._pending = {}
             if self in self.engine._residents:
                 self.engine._residents.remove(self)
             _check(st, "ms_resident_stop")
 
+
+# tensors of engines whose kernel would not stop (kept for the process)
+_never_freed = []
 
 _live_engines = weakref.WeakSet()
 
