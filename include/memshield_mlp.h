@@ -45,7 +45,11 @@ typedef struct ms_mlp_shape {
  * the total element count (0 for an invalid shape). */
 uint64_t ms_mlp_offsets(const ms_mlp_shape *shape, uint64_t offsets[7]);
 
-/* Bytes of scratch a call needs for batches of up to max_batch rows. */
+/* Bytes of scratch a call needs for batches of up to max_batch rows: the
+ * activations and their gradients, plus a fixed 8 MiB for the float32
+ * partial products of matrix products that split their K range over
+ * several workgroups.  Calls that share a workspace must not overlap on the
+ * device (one workspace per stream). */
 uint64_t ms_mlp_workspace_bytes(const ms_mlp_shape *shape, int32_t max_batch);
 
 /* Forward pass: logits[batch][V] (float32). */
