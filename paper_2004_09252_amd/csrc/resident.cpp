@@ -70,7 +70,9 @@ struct ms_resident {
   uint32_t n_keys = 1;
   bool launched = false;
   std::mutex mu;                  // producers
-  uint64_t next_pos = 0;
+  // written under `mu` by producers; read without it by ms_resident_poll,
+  // which must not contend with producers for the lock
+  std::atomic<uint64_t> next_pos{0};
 };
 
 namespace {
@@ -516,7 +518,7 @@ ms_status ms_resident_submit_keyed(ms_resident* r, uint32_t key_index,
   if (load_acq(&r->hctl->error)) return MS_EDEVICE;
   if (kernel_exited(r)) return MS_ECLOSED;
   std::lock_guard<std::mutex> lk(r->mu);
-  const uint64_t p0 = r->next_pos;
+  const uint64_t p0 = r->next_pos.load(std::memory_order_relaxed);
   // every slot must have completed its previous occupant (position - depth)
   for (uint64_t q = p0; q < p0 + m; ++q)
     if (q >= depth && load_acq(&r->completed[q & (depth - 1)]) < q - depth + 1)
@@ -543,7 +545,7 @@ ms_status ms_resident_submit_keyed(ms_resident* r, uint32_t key_index,
     x.seq = q;
   }
   store_rel(&r->hctl->published, p0 + m);
-  r->next_pos = p0 + m;
+  r->next_pos.store(p0 + m, std::memory_order_release);
   if (ticket_out) *ticket_out = ((p0 + 1) << kTicketCountBits) | m;
   return MS_OK;
 }
@@ -552,11 +554,7 @@ ms_status ms_resident_poll(ms_resident* r, const ms_ticket* tickets, size_t n,
                            int32_t* done_out, uint64_t timeout_ns) {
   if (!r || (n && (!tickets || !done_out))) return MS_EINVAL;
   const uint64_t depth = r->cfg.ring_depth;
-  uint64_t issued;
-  {
-    std::lock_guard<std::mutex> lk(r->mu);
-    issued = r->next_pos;
-  }
+  const uint64_t issued = r->next_pos.load(std::memory_order_acquire);
   for (size_t i = 0; i < n; ++i) {
     const uint64_t m = tickets[i] & ((1ull << kTicketCountBits) - 1);
     const uint64_t p1 = tickets[i] >> kTicketCountBits;
