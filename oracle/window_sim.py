@@ -141,9 +141,3 @@ def final_plaintext(n_pages: int, pages, words, values) -> np.ndarray:
                       np.asarray(values, dtype=np.uint64))
     return mem.astype("<u8").view(np.uint8).reshape(n_pages, 4096)
 
-
-def fault_deltas(fault_log) -> list:
-    """Successive differences of faulting page ids (the predictor's input
-    and target sequence)."""
-    ps = [p for _, p in fault_log]
-    return [b - a for a, b in zip(ps, ps[1:])]

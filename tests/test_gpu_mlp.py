@@ -87,25 +87,28 @@ def test_backward_matches_reference(pred):
 
 
 def test_adam_step_matches_reference(pred):
+    """Three GPU Adam steps against oracle.mlp_ref.adam_step (which
+    tests/test_mlp_oracle.py pins to torch.optim.Adam), same gradient each
+    step, parameters compared tensor by tensor."""
     _note("adam")
     import torch
     _load(pred, 4)
     rng = np.random.default_rng(44)
     g = rng.normal(0, 1e-2, pred.n_params).astype(np.float32)
-    w0 = pred.master.cpu().numpy().astype(np.float64)
+    w0 = pred.master.cpu()
     pred.grads.copy_(torch.from_numpy(g))
     for _ in range(3):
         pred.adam(lr=1e-3)
-    got = pred.master.cpu().numpy()
-    p = {"w": w0.copy()}
-    m = {"w": np.zeros_like(w0)}
-    v = {"w": np.zeros_like(w0)}
+    got = pred.unpack(pred.master.cpu())
+    p = {k: t.numpy().astype(np.float64) for k, t in pred.unpack(w0).items()}
+    gd = {k: t.numpy().astype(np.float64)
+          for k, t in pred.unpack(torch.from_numpy(g)).items()}
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(x) for k, x in p.items()}
     for t in range(1, 4):
-        m["w"] = 0.9 * m["w"] + 0.1 * g
-        v["w"] = 0.999 * v["w"] + 0.001 * g.astype(np.float64) ** 2
-        p["w"] = p["w"] - 1e-3 * (m["w"] / (1 - 0.9 ** t)) / (
-            np.sqrt(v["w"] / (1 - 0.999 ** t)) + 1e-8)
-    assert np.max(np.abs(got - p["w"])) < 1e-6
+        mlp_ref.adam_step(p, gd, m, v, t, lr=1e-3)
+    for k in mlp_ref.PARAMS:
+        assert np.max(np.abs(got[k].numpy() - p[k])) < 1e-6, k
     want = pred.master.cpu().to(torch.bfloat16)
     assert torch.equal(pred.params.cpu().view(torch.int16),
                        want.view(torch.int16))
