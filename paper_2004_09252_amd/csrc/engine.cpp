@@ -216,6 +216,40 @@ bool resolve_key(ms_ctx* c, ms_key k, uint32_t* slot) {
   return true;
 }
 
+// A synchronous call pins the key-table rows it uses from its handle check
+// until its launches are on their streams: under the key lock it re-checks
+// each handle and takes a reference.  ms_key_destroy then either sees the
+// reference (MS_EBUSY) or runs after the launches were enqueued, so that its
+// device synchronization covers them; a destroyed and reused row can never
+// reach a launch that resolved the old handle.
+ms_status pin_keys(ms_ctx* c, const ms_key* handles, size_t stride_bytes,
+                   const uint32_t* slots, size_t n) {
+  std::lock_guard<std::mutex> lk(c->key_mu);
+  const uint8_t* h = reinterpret_cast<const uint8_t*>(handles);
+  for (size_t i = 0; i < n; ++i) {
+    ms_key k;
+    std::memcpy(&k, h + i * stride_bytes, sizeof(k));
+    if (!c->key_live[slots[i]] || c->key_gen[slots[i]] != (uint32_t)(k >> 32))
+      return MS_ENOKEY;
+  }
+  for (size_t i = 0; i < n; ++i) c->key_refs[slots[i]].fetch_add(1);
+  return MS_OK;
+}
+
+void unpin_keys(ms_ctx* c, const uint32_t* slots, size_t n) {
+  for (size_t i = 0; i < n; ++i) c->key_refs[slots[i]].fetch_sub(1);
+}
+
+// Releases pinned rows when the call returns, on every path.
+struct KeyPins {
+  ms_ctx* c;
+  const uint32_t* slots;
+  size_t n = 0;
+  ~KeyPins() {
+    if (n) unpin_keys(c, slots, n);
+  }
+};
+
 ms_status check_nonce(ms_ctx* c, const ms_nonce* n, uint64_t n_pages) {
   if (!n) return MS_EINVAL;
   if (n->kind == MS_NONCE_ARRAY) {
@@ -321,16 +355,18 @@ void free_slot(BatchSlot& s) {
   s = BatchSlot();
 }
 
-// Lay the requests out in the slot's pinned buffer. Empty requests are
-// skipped.  Returns the number of bytes to copy (0 when there is no work).
-size_t fill_slot(BatchSlot& s, const ms_request* const* reqs,
-                 const uint32_t* key_slots, size_t n, uint64_t* total_out) {
-  auto* hdr = reinterpret_cast<ms::DevBatchHdr*>(s.host);
+// Lay the requests out as a batch header and request records in `host`
+// (pinned).  Empty requests are skipped.  Returns the number of bytes to
+// copy (0 when there is no work).  req(i) returns request i.
+template <class Req>
+size_t fill_descriptors(uint8_t* host, Req req, const uint32_t* key_slots,
+                        size_t n, uint64_t* total_out) {
+  auto* hdr = reinterpret_cast<ms::DevBatchHdr*>(host);
   auto* dr = reinterpret_cast<ms::DevReq*>(hdr + 1);
   uint64_t total = 0;
   uint32_t m = 0;
   for (size_t i = 0; i < n; ++i) {
-    const ms_request& r = *reqs[i];
+    const ms_request& r = req(i);
     if (r.n_pages == 0) continue;
     ms::DevReq& d = dr[m++];
     d.src = reinterpret_cast<uint64_t>(r.src);
@@ -357,6 +393,45 @@ size_t fill_slot(BatchSlot& s, const ms_request* const* reqs,
   *total_out = total;
   if (m == 0) return 0;
   return sizeof(ms::DevBatchHdr) + (size_t)m * sizeof(ms::DevReq);
+}
+
+size_t fill_slot(BatchSlot& s, const ms_request* const* reqs,
+                 const uint32_t* key_slots, size_t n, uint64_t* total_out) {
+  return fill_descriptors(
+      s.host, [reqs](size_t i) -> const ms_request& { return *reqs[i]; },
+      key_slots, n, total_out);
+}
+
+// Destinations of a batch must not overlap each other, nor any source other
+// than their own request's (in place is allowed).  `d` is working storage
+// (cleared here; no allocation while its capacity covers n).
+ms_status check_batch_ranges(const ms_request* reqs, size_t n,
+                             std::vector<std::pair<uintptr_t, uint64_t>>& d) {
+  d.clear();
+  for (size_t i = 0; i < n; ++i)
+    if (reqs[i].n_pages)
+      d.emplace_back(reinterpret_cast<uintptr_t>(reqs[i].dst),
+                     reqs[i].n_pages * MS_PAGE_SIZE);
+  std::sort(d.begin(), d.end());
+  for (size_t i = 1; i < d.size(); ++i)
+    if (d[i - 1].first + d[i - 1].second > d[i].first) return MS_EINVAL;
+  for (size_t i = 0; i < n; ++i) {
+    if (!reqs[i].n_pages) continue;
+    const uintptr_t s = reinterpret_cast<uintptr_t>(reqs[i].src);
+    const uintptr_t own = reinterpret_cast<uintptr_t>(reqs[i].dst);
+    const uint64_t nb = reqs[i].n_pages * MS_PAGE_SIZE;
+    // destinations are disjoint and sorted, so their ends are sorted too:
+    // walk back from the last one that starts before this source ends
+    auto it = std::lower_bound(d.begin(), d.end(),
+                               std::make_pair(s + nb, (uint64_t)0));
+    while (it != d.begin()) {
+      --it;
+      if (it->first + it->second <= s) break;
+      if (it->first == own && own == s) continue;  // in place
+      return MS_EINVAL;
+    }
+  }
+  return MS_OK;
 }
 
 // Capture [copy descriptors H2D] -> [fused kernel] for this slot and tiling.
@@ -811,6 +886,8 @@ ms_status plain_call(ms_ctx* c, ms_key key, const void* src, void* dst,
   uint32_t slot = 0;
   st = check_request(c, r, &slot, false);
   if (st) return st;
+  if ((st = pin_keys(c, &key, sizeof(ms_key), &slot, 1))) return st;
+  KeyPins pins{c, &slot, 1};
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   return launch_plain_run(c, slot, src, dst, n_pages, *nonce, s);
 }
@@ -945,6 +1022,7 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
     c->sync_slots.resize(4);
     for (auto& s : c->sync_slots)
       if (!st) st = alloc_slot(s, cfg.max_batch_requests);
+
     c->serve_slots.resize(cfg.inflight_batches);
     for (auto& s : c->serve_slots)
       if (!st) st = alloc_slot(s, cfg.max_batch_requests);
@@ -1076,34 +1154,14 @@ ms_status ms_process_batch(ms_ctx* c, const ms_request* reqs, size_t n,
     if (st) return st;
     rp[i] = &reqs[i];
   }
-  // destinations must not overlap each other, nor any source other than
-  // their own request's (in place is allowed)
   {
     std::vector<std::pair<uintptr_t, uint64_t>> d;
-    for (size_t i = 0; i < n; ++i)
-      if (reqs[i].n_pages)
-        d.emplace_back(reinterpret_cast<uintptr_t>(reqs[i].dst),
-                       reqs[i].n_pages * MS_PAGE_SIZE);
-    std::sort(d.begin(), d.end());
-    for (size_t i = 1; i < d.size(); ++i)
-      if (d[i - 1].first + d[i - 1].second > d[i].first) return MS_EINVAL;
-    for (size_t i = 0; i < n; ++i) {
-      if (!reqs[i].n_pages) continue;
-      const uintptr_t s = reinterpret_cast<uintptr_t>(reqs[i].src);
-      const uintptr_t own = reinterpret_cast<uintptr_t>(reqs[i].dst);
-      const uint64_t nb = reqs[i].n_pages * MS_PAGE_SIZE;
-      // destinations are disjoint and sorted, so their ends are sorted too:
-      // walk back from the last one that starts before this source ends
-      auto it = std::lower_bound(d.begin(), d.end(),
-                                 std::make_pair(s + nb, (uint64_t)0));
-      while (it != d.begin()) {
-        --it;
-        if (it->first + it->second <= s) break;
-        if (it->first == own && own == s) continue;  // in place
-        return MS_EINVAL;
-      }
-    }
+    d.reserve(n);
+    if ((st = check_batch_ranges(reqs, n, d))) return st;
   }
+  if ((st = pin_keys(c, &reqs[0].key, sizeof(ms_request), ks.data(), n)))
+    return st;
+  KeyPins pins{c, ks.data(), n};
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   std::lock_guard<std::mutex> lk(c->batch_mu);
   BatchSlot& slot = c->sync_slots[c->sync_next];
@@ -1371,6 +1429,13 @@ const ms_config& ms_internal_config(ms_ctx* c) { return c->cfg; }
 ms_status ms_internal_sticky(ms_ctx* c) { return check_sticky(c); }
 bool ms_internal_resolve_key(ms_ctx* c, ms_key key, uint32_t* slot) {
   return resolve_key(c, key, slot);
+}
+ms_status ms_internal_pin_key(ms_ctx* c, ms_key key, uint32_t* slot) {
+  if (!resolve_key(c, key, slot)) return MS_ENOKEY;
+  return pin_keys(c, &key, sizeof(key), slot, 1);
+}
+void ms_internal_unpin_key(ms_ctx* c, uint32_t slot) {
+  unpin_keys(c, &slot, 1);
 }
 ms_status ms_internal_launch_plain(ms_ctx* c, uint32_t key_slot,
                                    const void* src, void* dst,

@@ -262,7 +262,13 @@ ms_status host_call(ms_ctx* c, ms_key key, const void* src, void* dst,
     return MS_EINVAL;
   }
   uint32_t slot = 0;
-  if (!ms_internal_resolve_key(c, key, &slot)) return MS_ENOKEY;
+  if ((st = ms_internal_pin_key(c, key, &slot))) return st;
+  // released once the launches below are enqueued (or failed)
+  struct Unpin {
+    ms_ctx* c;
+    uint32_t slot;
+    ~Unpin() { ms_internal_unpin_key(c, slot); }
+  } unpin{c, slot};
   // Measured on an MI355X host link (host -> host, 1 MiB to 4 GiB): the
   // mapped kernel with host_mapped_waves = 128 matches or passes the staged
   // pipeline at every size (49 GB/s against 47-48 from 1 GiB up, 40 against

@@ -23,6 +23,11 @@ ms_status ms_internal_dev_err(ms_ctx* c, hipError_t e);
 ms_status ms_internal_sticky(ms_ctx* c);
 // Key handle -> key-table row; false for an unknown or stale handle.
 bool ms_internal_resolve_key(ms_ctx* c, ms_key key, uint32_t* slot);
+// Resolve and pin a key handle for a synchronous call: until the matching
+// unpin, ms_key_destroy of that handle returns MS_EBUSY.  Unpin once the
+// call's launches are enqueued.  MS_ENOKEY for an unknown or stale handle.
+ms_status ms_internal_pin_key(ms_ctx* c, ms_key key, uint32_t* slot);
+void ms_internal_unpin_key(ms_ctx* c, uint32_t slot);
 // One plain launch (split where a launch would exceed its page limit) of
 // n_pages pages from src to dst, both GPU-visible addresses, page p taking
 // the nonce of page p of `nonce`, with at most `max_waves` waves (0 = as

@@ -35,6 +35,8 @@ COMMON = [os.path.join(CSRC, "engine.cpp"),
           os.path.join(MOCK, "mock_hip.cpp"),
           os.path.join(MOCK, "mock_kernels.cpp")]
 SCHED_SOURCES = COMMON + [os.path.join(MOCK, "sched_stress.cpp")]
+KEY_RACE_SOURCES = COMMON + [os.path.join(CSRC, "host_pages.cpp"),
+                             os.path.join(MOCK, "key_race.cpp")]
 RESIDENT_SOURCES = COMMON + [os.path.join(CSRC, "host_pages.cpp"),
                              os.path.join(CSRC, "resident.cpp"),
                              os.path.join(MOCK, "mock_hsa.cpp"),
@@ -96,3 +98,15 @@ def test_resident_engine_host_logic_under_thread_sanitizer(tmp_path):
     # the small ring must have filled: producers met MS_EAGAIN
     retries = int(out.split("eagain_retries=")[1].split()[0])
     assert retries > 0, out
+
+
+def test_key_destroy_racing_synchronous_calls(tmp_path):
+    """ms_key_destroy + reload of the same key-table row against
+    synchronous calls (plain, fused batch, host pages) that keep using the
+    destroyed key's newest handle: every call that succeeds must have
+    ciphered with that key, and ThreadSanitizer must report nothing."""
+    if not _tsan_available(tmp_path):
+        pytest.skip("g++ with ThreadSanitizer not available")
+    out = _run_clean(_build(tmp_path, KEY_RACE_SOURCES, "key_race"))
+    cycles = int(out.split("cycles=")[1].split()[0])
+    assert cycles > 0, out
