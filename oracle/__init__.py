@@ -9,10 +9,11 @@ none of the method's arithmetic.
 
 Contents:
   * ``chacha20_oracle.c`` - scalar C ChaCha block function and page XOR
-    (paper section 4.4), built with gcc into ``_build/liboracle_chacha.so``
+    (paper section 4.4), and the Salsa20 block function and page XOR of the
+    engine's second cipher, built with gcc into ``_build/liboracle_chacha.so``
     and called through ctypes;
-  * ``chacha_py`` - a second, pure-Python ChaCha written separately, for tiny
-    inputs;
+  * ``chacha_py`` and ``salsa_py`` - second, pure-Python ChaCha and Salsa20
+    written separately, for tiny inputs;
   * ``nonces`` - the page-nonce readings of the paper's 128-bit seed value;
   * ``window_sim`` - the sliding-window decrypt-on-fault model (sections 4.2,
     4.3);
@@ -70,6 +71,17 @@ def _load():
                                                    u8p, ctypes.c_uint64,
                                                    ctypes.c_int]
             lib.oracle_cipher_pages_mt.restype = ctypes.c_int
+            lib.oracle_salsa_block.argtypes = [u8p, u8p, ctypes.c_uint64,
+                                               ctypes.c_int, u8p]
+            lib.oracle_salsa_block.restype = None
+            lib.oracle_cipher_pages_with.argtypes = [
+                ctypes.c_int, u8p, u8p, ctypes.c_int, u8p, u8p,
+                ctypes.c_uint64]
+            lib.oracle_cipher_pages_with.restype = None
+            lib.oracle_cipher_pages_mt_with.argtypes = [
+                ctypes.c_int, u8p, u8p, ctypes.c_int, u8p, u8p,
+                ctypes.c_uint64, ctypes.c_int]
+            lib.oracle_cipher_pages_mt_with.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -97,12 +109,31 @@ def chacha_block(key, counter: int, nonce, rounds: int = 20) -> bytes:
     return out.tobytes()
 
 
+CIPHERS = {"chacha": 0, "salsa": 1}
+
+
+def salsa_block(key, nonce8, counter: int, rounds: int = 20) -> bytes:
+    """One 64-byte Salsa20 keystream block for a 64-bit nonce and a 64-bit
+    block counter (the engine's second cipher)."""
+    k = _as_u8(key)
+    n = _as_u8(nonce8)
+    assert k.size == KEY_BYTES and n.size == 8
+    assert rounds > 0 and rounds % 2 == 0
+    out = np.zeros(BLOCK_BYTES, dtype=np.uint8)
+    _load().oracle_salsa_block(_ptr(k), _ptr(n), counter & (2**64 - 1),
+                               rounds, _ptr(out))
+    return out.tobytes()
+
+
 def cipher_pages(key, nonces, data, rounds: int = 20, threads: int = 1,
-                 out: np.ndarray | None = None) -> np.ndarray:
+                 out: np.ndarray | None = None,
+                 cipher: str = "chacha") -> np.ndarray:
     """XOR each 4096-byte page with its 64 keystream blocks (section 4.4).
 
     ``nonces`` is (n_pages, 12) uint8, ``data`` is (n_pages, 4096) uint8 (or
     anything reshapeable to it).  Encryption and decryption are the same call.
+    ``cipher`` is "chacha" (the paper's) or "salsa" (Salsa20: nonce = page
+    nonce bytes 0..7, block counter = page nonce word 2 * 2^32 + j).
     """
     k = _as_u8(key)
     assert k.size == KEY_BYTES
@@ -116,29 +147,34 @@ def cipher_pages(key, nonces, data, rounds: int = 20, threads: int = 1,
         assert out.dtype == np.uint8 and out.flags.c_contiguous
         assert out.size == d.size
     lib = _load()
+    cid = CIPHERS[cipher]
     if threads <= 1:
-        lib.oracle_cipher_pages(_ptr(k), _ptr(n), rounds, _ptr(d), _ptr(out),
-                                d.shape[0])
+        lib.oracle_cipher_pages_with(cid, _ptr(k), _ptr(n), rounds, _ptr(d),
+                                     _ptr(out), d.shape[0])
     else:
-        lib.oracle_cipher_pages_mt(_ptr(k), _ptr(n), rounds, _ptr(d),
-                                   _ptr(out), d.shape[0], int(threads))
+        lib.oracle_cipher_pages_mt_with(cid, _ptr(k), _ptr(n), rounds,
+                                        _ptr(d), _ptr(out), d.shape[0],
+                                        int(threads))
     return out.reshape(d.shape)
 
 
 def cipher_pages_timed(key, nonces, data, rounds: int = 20,
-                       threads: int = 1) -> tuple[np.ndarray, int]:
+                       threads: int = 1,
+                       cipher: str = "chacha") -> tuple[np.ndarray, int]:
     """Like ``cipher_pages`` but also returns the thread count actually used."""
     k = _as_u8(key)
     d = _as_u8(data).reshape(-1, PAGE_BYTES)
     n = _as_u8(nonces).reshape(-1, NONCE_BYTES)
     out = np.empty_like(d)
-    used = _load().oracle_cipher_pages_mt(_ptr(k), _ptr(n), rounds, _ptr(d),
-                                          _ptr(out), d.shape[0], int(threads))
+    used = _load().oracle_cipher_pages_mt_with(
+        CIPHERS[cipher], _ptr(k), _ptr(n), rounds, _ptr(d), _ptr(out),
+        d.shape[0], int(threads))
     return out, used
 
 
 from .nonces import nonces_linear, nonce_linear  # noqa: E402
 
-__all__ = ["build", "chacha_block", "cipher_pages", "cipher_pages_timed",
+__all__ = ["build", "chacha_block", "salsa_block", "cipher_pages",
+           "cipher_pages_timed",
            "nonces_linear", "nonce_linear", "PAGE_BYTES", "BLOCK_BYTES",
            "NONCE_BYTES", "KEY_BYTES"]

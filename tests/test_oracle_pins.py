@@ -263,3 +263,151 @@ def test_golden_tiny_digest_reproduces():
     t = workloads.tiny(seed=seed, n_pages=n)
     enc = oracle.cipher_pages(t.key, t.nonces, t.data)
     assert hashlib.sha256(enc.tobytes()).hexdigest() == digest
+
+
+# --- Salsa20, the engine's second cipher ---------------------------------
+# A Salsa20 page under the 12-byte page nonce N is the Salsa20 stream with
+# the 8-byte nonce N[0:8] from block counter LE32(N[8:12]) * 2^32 over the
+# page's 4096 bytes.  Pinned by libgcrypt (whose stream starts at counter 0:
+# pages whose third nonce word is 0) and libnettle (any starting counter),
+# by the pure-Python Salsa20 and by planted mistakes.
+
+salsa_libs = pytest.mark.skipif(not (cl.HAVE_GCRYPT and cl.HAVE_NETTLE),
+                                reason="libgcrypt or libnettle not present")
+
+
+@salsa_libs
+@pytest.mark.parametrize("rounds", [20, 12])
+def test_salsa_page_matches_gcrypt_stream(rounds):
+    key = _rand(32)
+    nonces = np.frombuffer(_rand(12 * 6), np.uint8).reshape(6, 12).copy()
+    nonces[:, 8:] = 0
+    data = np.frombuffer(_rand(4096 * 6), np.uint8).reshape(6, 4096)
+    got = oracle.cipher_pages(key, nonces, data, rounds=rounds,
+                              cipher="salsa")
+    for p in range(6):
+        want = cl.gcrypt_salsa20(key, nonces[p, :8].tobytes(),
+                                 data[p].tobytes(), rounds)
+        assert got[p].tobytes() == want
+
+
+@salsa_libs
+@pytest.mark.parametrize("rounds", [20, 12])
+def test_salsa_page_matches_nettle_from_high_counter(rounds):
+    key = _rand(32)
+    nonces = np.frombuffer(_rand(12 * 6), np.uint8).reshape(6, 12).copy()
+    nonces[0, 8:] = 255      # counter high word 0xffffffff
+    data = np.frombuffer(_rand(4096 * 6), np.uint8).reshape(6, 4096)
+    got = oracle.cipher_pages(key, nonces, data, rounds=rounds,
+                              cipher="salsa")
+    for p in range(6):
+        high = int.from_bytes(nonces[p, 8:].tobytes(), "little") << 32
+        want = cl.nettle_salsa20(key, nonces[p, :8].tobytes(), high,
+                                 data[p].tobytes(), rounds)
+        assert got[p].tobytes() == want
+
+
+@salsa_libs
+def test_salsa_libraries_agree_and_nettle_counter_words():
+    """The two libraries agree from counter 0, and nettle started at counter
+    1 equals libgcrypt's second block: words 8 and 9 of nettle's state are
+    the block counter, as the high-counter pin assumes."""
+    key, n8 = _rand(32), _rand(8)
+    a = cl.gcrypt_salsa20(key, n8, bytes(4096))
+    assert cl.nettle_salsa20(key, n8, 0, bytes(4096)) == a
+    assert cl.nettle_salsa20(key, n8, 1, bytes(64)) == a[64:128]
+    assert cl.nettle_salsa20(key, n8, 63, bytes(64)) == a[4032:]
+
+
+@pytest.mark.parametrize("rounds", [20, 12, 8])
+def test_salsa_python_oracle_agrees_with_c_oracle(rounds):
+    from oracle import salsa_py
+    key = _rand(32)
+    nonces = np.frombuffer(_rand(12 * 2), np.uint8).reshape(2, 12)
+    data = np.frombuffer(_rand(4096 * 2), np.uint8).reshape(2, 4096)
+    got = oracle.cipher_pages(key, nonces, data, rounds=rounds,
+                              cipher="salsa")
+    for p in range(2):
+        want = salsa_py.cipher_page(key, nonces[p].tobytes(),
+                                    data[p].tobytes(), rounds)
+        assert got[p].tobytes() == want
+    for ctr in (0, 63, 2**32 - 1, 2**32, 2**64 - 1):
+        n8 = _rand(8)
+        assert oracle.salsa_block(key, n8, ctr, rounds) == \
+            salsa_py.block(key, n8, ctr, rounds)
+
+
+def test_salsa_invariants():
+    """Same function both ways, a distinct keystream from ChaCha's under the
+    same key and nonce, and different keystreams for nonces that differ only
+    in the word that becomes the counter's high half."""
+    w = workloads.tiny(seed=13, n_pages=4)
+    enc = oracle.cipher_pages(w.key, w.nonces, w.data, cipher="salsa")
+    assert np.array_equal(oracle.cipher_pages(w.key, w.nonces, enc,
+                                              cipher="salsa"), w.data)
+    cha = oracle.cipher_pages(w.key, w.nonces, w.data)
+    assert abs(_bit_fraction(enc.tobytes(), cha.tobytes()) - 0.5) < 0.02
+    n2 = w.nonces.copy()
+    n2[:, 8] ^= 1
+    other = oracle.cipher_pages(w.key, n2, w.data, cipher="salsa")
+    assert abs(_bit_fraction(enc.tobytes(), other.tobytes()) - 0.5) < 0.02
+    # blocks are independent: block j of a page is the block at counter j
+    ks = oracle.cipher_pages(w.key, w.nonces[:1], np.zeros((1, 4096),
+                                                           np.uint8),
+                             cipher="salsa")[0]
+    high = int.from_bytes(w.nonces[0, 8:].tobytes(), "little") << 32
+    for j in (0, 1, 37, 63):
+        assert ks[64 * j:64 * j + 64].tobytes() == oracle.salsa_block(
+            w.key, w.nonces[0, :8], high + j)
+
+
+SALSA_MUTATIONS = [
+    ("x[b] ^= rotate_left(x[a] + x[d], 7);",
+     "x[b] ^= rotate_left(x[a] + x[d], 8);"),
+    ("x[a] ^= rotate_left(x[d] + x[c], 18);",
+     "x[a] ^= rotate_left(x[d] + x[c], 16);"),
+    ("x[c] ^= rotate_left(x[b] + x[a], 9);",
+     "x[c] += rotate_left(x[b] + x[a], 9);"),
+    ("salsa_quarter(work, 5, 9, 13, 1);", "salsa_quarter(work, 5, 9, 1, 13);"),
+    ("salsa_quarter(work, 10, 11, 8, 9);",
+     "salsa_quarter(work, 10, 11, 9, 8);"),
+    ("input[8] = (uint32_t)(counter & 0xffffffffu);",
+     "input[8] = (uint32_t)(counter & 0xffffffffu) + 1;"),
+    ("input[9] = (uint32_t)(counter >> 32);", "input[9] = 0;"),
+    ("input[11 + i] = read_le32(key + 16 + 4 * i);",
+     "input[11 + i] = read_le32(key + 4 * i);"),
+    ("input[6] = read_le32(nonce8);", "input[6] = read_le32(nonce8 + 4);"),
+    ("input[5] = read_le32((const uint8_t *)sigma + 4);",
+     "input[5] = read_le32((const uint8_t *)sigma + 8);"),
+    ("write_le32(out + 4 * i, work[i] + input[i]);\n}\n\n/* One page with "
+     "Salsa20", "write_le32(out + 4 * i, work[i] ^ input[i]);\n}\n\n/* One "
+     "page with Salsa20"),
+]
+
+
+@salsa_libs
+@pytest.mark.parametrize("old,new", SALSA_MUTATIONS)
+def test_salsa_pins_catch_planted_mistakes(tmp_path, old, new):
+    import ctypes
+    src = open(os.path.join(os.path.dirname(oracle.__file__),
+                            "chacha20_oracle.c")).read()
+    assert src.count(old) == 1, old
+    mutated = src.replace(old, new, 1)
+    c = tmp_path / "m.c"
+    so = tmp_path / "m.so"
+    c.write_text(mutated)
+    subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-pthread",
+                           str(c), "-o", str(so)])
+    lib = ctypes.CDLL(str(so))
+    lib.oracle_salsa_block.argtypes = [ctypes.c_char_p, ctypes.c_char_p,
+                                       ctypes.c_uint64, ctypes.c_int,
+                                       ctypes.c_void_p]
+    caught = False
+    rng = np.random.default_rng(98)
+    for ctr in (0, 1, 63, (7 << 32) + 5):
+        key, n8 = rng.bytes(32), rng.bytes(8)
+        out = ctypes.create_string_buffer(64)
+        lib.oracle_salsa_block(key, n8, ctr, 20, out)
+        if out.raw != cl.nettle_salsa20(key, n8, ctr, bytes(64)):
+            caught = True
+    assert caught, "library pin missed a planted mistake"
