@@ -222,6 +222,29 @@ ms_status ms_process_batch(ms_ctx *ctx, const ms_request *reqs, size_t n,
                            void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the fused
+ * launch of ms_process_batch, with the same checks and the same bytes out,
+ * that allocates nothing.  Its request descriptors (a 64-byte header plus 64
+ * bytes per request) go to a device array of fixed size built into the
+ * library, one per GPU, held until the process ends, through a pinned host
+ * buffer that ms_init allocated; the kernel is launched directly (no graph)
+ * on `stream` after a host-to-device copy of the descriptors on the same
+ * stream.  At most MS_STATIC_BATCH_MAX_REQUESTS requests (256 KiB of
+ * descriptors), else MS_EINVAL.  Before it reuses the host buffer, a call
+ * waits on the host until the previous call's copy and kernel are done.
+ * Calls on one GPU share the device array: calls on different streams that
+ * overlap on the device race (the later copy may overwrite descriptors that
+ * the earlier kernel still reads), so order them on one stream or
+ * synchronize between them; this holds across contexts on the same GPU.
+ * Ownership of pages and nonce arrays as for ms_process_batch.
+ * Errors: MS_EINVAL, MS_ENOKEY, MS_ENOTSUP, MS_EDEVICE.
+ */
+#define MS_STATIC_BATCH_MAX_REQUESTS 4096u
+ms_status ms_process_batch_static(ms_ctx *ctx, const ms_request *reqs,
+                                  size_t n, void *stream);
+
+/*
  * Asynchronous serving path (continuous batching).  ms_submit validates the
  * requests and queues them; it never blocks.  The engine runs submitted work
  * on its own streams, which do not wait for the caller's streams: a

@@ -43,6 +43,8 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 constexpr uint32_t kMaxKeysLimit = 65536;
+static_assert(ms::kStaticBatchMaxRequests == MS_STATIC_BATCH_MAX_REQUESTS,
+              "static batch limit");
 
 inline bool hip_ok(hipError_t e) { return e == hipSuccess; }
 
@@ -124,6 +126,16 @@ struct ms_ctx {
   std::mutex batch_mu;
   std::vector<BatchSlot> sync_slots;
   size_t sync_next = 0;
+
+  // ---- ms_process_batch_static: no allocation after ms_init ----
+  std::mutex static_mu;
+  void* d_static = nullptr;        // this device's descriptor array
+                                   // (address of `scratch`, page_cipher.hip)
+  uint8_t* h_static = nullptr;     // pinned staging of the same size
+  hipEvent_t static_done = nullptr;  // after the last launch that read it
+  bool static_used = false;
+  std::vector<uint32_t> static_slots;  // capacity kStaticBatchMaxRequests
+  std::vector<std::pair<uintptr_t, uint64_t>> static_ranges;  // same
 
   // ---- tuning ----
   std::mutex tune_mu;
@@ -1022,6 +1034,21 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
     c->sync_slots.resize(4);
     for (auto& s : c->sync_slots)
       if (!st) st = alloc_slot(s, cfg.max_batch_requests);
+    // ms_process_batch_static: the device array's address on this device
+    // (hipGetSymbolAddress, with the device current), its pinned staging
+    // and the working storage of its checks
+    if (!st && !hip_ok(ms::static_batch_scratch(&c->d_static))) st = MS_EDEVICE;
+    if (!st && !hip_ok(hipHostMalloc(reinterpret_cast<void**>(&c->h_static),
+                                     ms::kStaticBatchBytes,
+                                     hipHostMallocDefault)))
+      st = MS_ENOMEM;
+    if (!st && !hip_ok(hipEventCreateWithFlags(&c->static_done,
+                                               hipEventDisableTiming)))
+      st = MS_EDEVICE;
+    if (!st) {
+      c->static_slots.resize(MS_STATIC_BATCH_MAX_REQUESTS);
+      c->static_ranges.reserve(MS_STATIC_BATCH_MAX_REQUESTS);
+    }
 
     c->serve_slots.resize(cfg.inflight_batches);
     for (auto& s : c->serve_slots)
@@ -1079,6 +1106,9 @@ ms_status ms_shutdown(ms_ctx* c) {
   }
   for (auto& s : c->sync_slots) free_slot(s);
   for (auto& s : c->serve_slots) free_slot(s);
+  // the device array of ms_process_batch_static stays with the device
+  if (c->static_done) (void)hipEventDestroy(c->static_done);
+  if (c->h_static) (void)hipHostFree(c->h_static);
   for (auto& s : c->serve_streams)
     if (s) (void)hipStreamDestroy(s);
   if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -1172,6 +1202,46 @@ ms_status ms_process_batch(ms_ctx* c, const ms_request* reqs, size_t n,
   const size_t copy = fill_slot(slot, rp.data(), ks.data(), n, &total);
   if (!copy) return MS_OK;
   return issue_slot(c, slot, copy, total, s, c->cfg.use_graphs != 0);
+}
+
+ms_status ms_process_batch_static(ms_ctx* c, const ms_request* reqs,
+                                  size_t n, void* stream) {
+  if (!c) return MS_EINVAL;
+  ms_status st = check_sticky(c);
+  if (st) return st;
+  if (n == 0) return MS_OK;
+  if (!reqs || n > MS_STATIC_BATCH_MAX_REQUESTS) return MS_EINVAL;
+  if (!c->d_static) return MS_ENOTSUP;
+  // everything below uses storage sized at ms_init: no allocation
+  std::lock_guard<std::mutex> lk(c->static_mu);
+  uint32_t* ks = c->static_slots.data();
+  for (size_t i = 0; i < n; ++i)
+    if ((st = check_request(c, reqs[i], &ks[i], true))) return st;
+  if ((st = check_batch_ranges(reqs, n, c->static_ranges))) return st;
+  if ((st = pin_keys(c, &reqs[0].key, sizeof(ms_request), ks, n))) return st;
+  KeyPins pins{c, ks, n};
+  // the pinned staging is rewritten only after the previous copy out of it
+  // (and the kernel that read the device array) has finished
+  if (c->static_used && !hip_ok(hipEventSynchronize(c->static_done)))
+    return dev_err(c, hipErrorUnknown);
+  uint64_t total = 0;
+  const size_t copy = fill_descriptors(
+      c->h_static, [reqs](size_t i) -> const ms_request& { return reqs[i]; },
+      ks, n, &total);
+  if (!copy) return MS_OK;
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  const Tuning t = tuning_for(c, total);
+  const uint32_t grid = grid_blocks_for(c, t, total);
+  hipError_t e = hipMemcpyAsync(c->d_static, c->h_static, copy,
+                                hipMemcpyHostToDevice, s);
+  if (hip_ok(e))
+    e = ms::launch_batch(static_cast<const ms::DevBatchHdr*>(c->d_static),
+                         c->d_keys, t.ppw, t.unroll, grid, (int)c->cfg.rounds,
+                         s);
+  if (hip_ok(e)) e = hipEventRecord(c->static_done, s);
+  if (!hip_ok(e)) return dev_err(c, e);
+  c->static_used = true;
+  return MS_OK;
 }
 
 ms_status ms_submit(ms_ctx* c, const ms_request* reqs, size_t n,

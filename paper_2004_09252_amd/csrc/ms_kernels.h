@@ -72,6 +72,15 @@ const void* plain_kernel_fn(uint32_t unroll, int rounds, uint32_t kind);
 // 0 if the runtime cannot say.
 uint32_t resident_waves_per_cu(const void* fn);
 
+// Descriptor array of ms_process_batch_static: one batch header and up to
+// kStaticBatchMaxRequests request records, a file-scope device array in
+// page_cipher.hip (one copy per device, for the life of the process).
+constexpr uint32_t kStaticBatchMaxRequests = 4096;
+constexpr size_t kStaticBatchBytes =
+    sizeof(DevBatchHdr) + (size_t)kStaticBatchMaxRequests * sizeof(DevReq);
+// The current device's address of that array (hipGetSymbolAddress).
+hipError_t static_batch_scratch(void** out);
+
 // Calibration probes.
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes,
                        uint32_t grid_blocks, hipStream_t stream);

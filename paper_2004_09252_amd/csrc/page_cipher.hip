@@ -401,6 +401,17 @@ hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
                          stream);
 }
 
+// Request descriptors of ms_process_batch_static.  Host code must not pass
+// this name to a kernel or a copy: on the host it only stands for the
+// symbol; its device address comes from static_batch_scratch.
+static __device__ __align__(256) uint8_t scratch[kStaticBatchBytes];
+
+hipError_t static_batch_scratch(void** out) {
+  if (!out) return hipErrorInvalidValue;
+  *out = nullptr;
+  return hipGetSymbolAddress(out, HIP_SYMBOL(scratch));
+}
+
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes,
                        uint32_t grid_blocks, hipStream_t stream) {
   (void)grid_blocks;  // one wave per 4 KiB chunk

@@ -154,6 +154,8 @@ _SIGS = {
                          _I32),
     "ms_process_batch": ([_P, ctypes.POINTER(ms_request), ctypes.c_size_t, _P],
                          _I32),
+    "ms_process_batch_static": ([_P, ctypes.POINTER(ms_request),
+                                 ctypes.c_size_t, _P], _I32),
     "ms_submit": ([_P, ctypes.POINTER(ms_request), ctypes.c_size_t,
                    ctypes.POINTER(_U64)], _I32),
     "ms_poll": ([_P, ctypes.POINTER(_U64), ctypes.c_size_t,
@@ -301,6 +303,14 @@ def _req_array(reqs):
 def ms_process_batch(ctx, reqs, stream=None) -> int:
     arr, n = _req_array(reqs)
     return _L().ms_process_batch(ctx, arr, n, stream)
+
+
+MS_STATIC_BATCH_MAX_REQUESTS = 4096
+
+
+def ms_process_batch_static(ctx, reqs, stream=None) -> int:
+    arr, n = _req_array(reqs)
+    return _L().ms_process_batch_static(ctx, arr, n, stream)
 
 
 def ms_submit(ctx, reqs):
@@ -796,6 +806,14 @@ class Engine:
     def process_batch(self, reqs, stream=None):
         _check(ms_process_batch(self.ctx, reqs, _stream_handle(stream)),
                "ms_process_batch")
+
+    def process_batch_static(self, reqs, stream=None):
+        """ms_process_batch without any allocation (descriptors in the
+        library's fixed device array); at most MS_STATIC_BATCH_MAX_REQUESTS
+        requests, and calls must not overlap on the device."""
+        _check(ms_process_batch_static(self.ctx, reqs,
+                                       _stream_handle(stream)),
+               "ms_process_batch_static")
 
     def submit(self, reqs) -> list:
         """Queue requests; those built by `request` keep their tensors alive

@@ -122,6 +122,16 @@ hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
   return hipSuccess;
 }
 
+// The device array of the allocation-free batch entry point: host memory
+// here, like every mock device buffer.
+alignas(256) static uint8_t g_static_scratch[kStaticBatchBytes];
+
+hipError_t static_batch_scratch(void** out) {
+  if (!out) return hipErrorInvalidValue;
+  *out = g_static_scratch;
+  return hipSuccess;
+}
+
 hipError_t launch_copy(const void*, void*, uint64_t, uint32_t, hipStream_t) {
   return hipErrorInvalidValue;
 }
