@@ -21,6 +21,16 @@ Fault events (window misses) are what the server observes, with or without
 prefetching, so the predictor's input sequence is the same in training and
 in use.
 
+Pre-decryptions go either into the same fused launches as the demand work,
+in program order, or (``hints=True``) to the engine as prefetch hints
+(ms_prefetch_hint): low-priority, droppable requests that run on the
+engine's own streams beside the demand launches, which never wait for them.
+A hint the engine drops is simply not a prefetch.  Before it hands a page
+over, the simulation makes sure the work that last wrote the page's stored
+ciphertext and the slot it fills has finished; a later use of the slot (a
+prefetch hit, or reuse after the page was pushed out unused) first waits for
+the hint's ticket.
+
 Background pre-encryption (the paper's conclusions suggest it as future
 work): after each window miss, while a client's reclaimable slots (free
 slots plus "clean" pages, whose current contents a background encryption
@@ -87,6 +97,17 @@ class PagedMemory:
         self.free = [deque(range(slots)) for _ in range(self.n_clients)]
         self.launches = 0
         self.pages_moved = 0
+        # hand-over to prefetch hints (module doc)
+        self.flushes = 0            # fused launches issued so far
+        self.done_flushes = 0       # ... known finished on the device
+        self.wrote_in = {}          # (client, page) -> flush of last encrypt
+        self.slot_used_in = {}      # (client, slot) -> flush of last use
+        self.hint_ticket = {}       # (client, slot) -> unfinished hint
+        self.hints_issued = 0
+        self.hints_dropped = 0
+        self.hint_waits = 0
+        self.flush_events = []      # (start, end) events of each launch
+        self.time_flushes = False
         self._reset_queue()
 
     def _reset_queue(self):
@@ -107,9 +128,59 @@ class PagedMemory:
 
     def alloc(self, c: int) -> int:
         s = self.free[c].popleft()
+        self.wait_hint(c, s)
         if (c, s) in self.slot_busy:
             self.flush()
         return s
+
+    def wait_hint(self, c: int, s: int) -> None:
+        """Wait until the prefetch hint that fills slot s (if any) is done."""
+        t = self.hint_ticket.pop((c, s), None)
+        if t is None:
+            return
+        st, done = self.eng.poll([t], timeout_s=30.0)
+        if st != ms.MS_OK or done[0] != 1:
+            raise RuntimeError("prefetch hint did not finish: status %d, "
+                               "state %d" % (st, done[0]))
+        self.hint_waits += 1
+
+    def hint(self, items) -> list:
+        """Pre-decrypt (client, page, slot) items as prefetch hints; returns
+        for each whether the engine took it (a dropped hint fills nothing).
+        The hints read the stored ciphertext and write the slots from the
+        engine's streams, which do not wait for this stream: queued work on
+        those pages or slots is launched first, and the stream is
+        synchronized if such work may still run."""
+        if not items:
+            return []
+        if any((c, p) in self.store_write or (c, s) in self.slot_busy
+               for c, p, s in items):
+            self.flush()
+        last = max(max(self.wrote_in.get((c, p), 0),
+                       self.slot_used_in.get((c, s), 0))
+                   for c, p, s in items)
+        if last > self.done_flushes:
+            torch.cuda.current_stream().synchronize()
+            self.done_flushes = self.flushes
+        reqs = [ms.request(self.keys[c], self.store, self.clear, 1,
+                           self._nonce(c, p), op=ms.MS_DECRYPT, client=c,
+                           src_offset_pages=c * self.n_pages + p,
+                           dst_offset_pages=self._gslot(c, s))
+                for c, p, s in items]
+        tickets = self.eng.prefetch_hint(reqs)
+        took = []
+        for (c, p, s), t in zip(items, tickets):
+            if t:
+                self.hint_ticket[(c, s)] = t
+                self.hints_issued += 1
+            else:
+                self.hints_dropped += 1
+            took.append(bool(t))
+        return took
+
+    def wait_all_hints(self) -> None:
+        for c, s in list(self.hint_ticket):
+            self.wait_hint(c, s)
 
     def release(self, c: int, s: int) -> None:
         self.free[c].append(s)
@@ -160,9 +231,22 @@ class PagedMemory:
     def flush(self) -> None:
         if self.reqs:
             arr = (ms.ms_request * len(self.reqs))(*self.reqs)
-            self.eng.process_batch(arr)
+            if self.time_flushes:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                self.eng.process_batch(arr)
+                e1.record()
+                self.flush_events.append((e0, e1))
+            else:
+                self.eng.process_batch(arr)
             self.launches += 1
             self.pages_moved += len(self.reqs)
+        self.flushes += 1
+        for cp in self.store_write:
+            self.wrote_in[cp] = self.flushes
+        for cs in self.slot_busy:
+            self.slot_used_in[cs] = self.flushes
         if self.zero:
             idx = torch.tensor(self.zero, dtype=torch.int64, device="cuda")
             self.clear.view(-1, PAGE).index_fill_(0, idx, 0)
@@ -199,22 +283,29 @@ def new_counters():
     return {"accesses": 0, "faults": 0, "first_touch": 0, "decrypts": 0,
             "encrypts": 0, "prefetch_issued": 0, "prefetch_hits": 0,
             "prefetch_wasted": 0, "events": 0, "encrypts_bg": 0,
-            "bg_wasted": 0, "evict_clean": 0}
+            "bg_wasted": 0, "evict_clean": 0, "prefetch_dropped": 0}
 
 
 def run(trace, window: int, mem: PagedMemory | None = None,
         prefetch_slots: int = 0, predictor=None, vocab: DeltaVocab | None = None,
         k: int = 8, predict_from: int = 0, stop: int | None = None,
         count_from: int = 0, record_events: bool = False,
-        min_prob: float = 0.0, bg_threshold: int = 0):
+        min_prob: float | None = None, bg_threshold: int = 0,
+        hints: bool = False):
     """Replay `trace` (workloads.AccessTrace) for steps [0, stop) with all
     clients in lockstep.  Prediction is active for steps >= predict_from,
     counters cover steps >= count_from.  Returns (counters, events, decisions)
     where events[c] is the list of fault-event pages of client c (if
-    recorded) and decisions maps (c, t) to the pages the predictor asked
-    for after step t.  Of the predictor's top-k deltas only those with a
-    softmax probability of at least `min_prob` are pre-decrypted.
+    recorded) and decisions maps (c, t) to the pages pre-decrypted after
+    step t.  Of the predictor's top-k deltas only those with a softmax
+    probability of at least `min_prob` (default: the predictor's own
+    min_prob) are pre-decrypted.  `hints` sends the pre-decryptions to the
+    engine as prefetch hints instead of the fused launches (module doc).
     `bg_threshold` > 0 turns on background pre-encryption (module doc)."""
+    if min_prob is None:
+        min_prob = predictor.min_prob if predictor is not None else 0.0
+    if hints and mem is None:
+        raise ValueError("hints need the page data on the GPU (mem)")
     C = trace.clients
     n = trace.pages_per_client
     stop = trace.steps if stop is None else stop
@@ -272,6 +363,8 @@ def run(trace, window: int, mem: PagedMemory | None = None,
                     cl.events.append(p)
                 if p in cl.pf:
                     s = cl.pf.pop(p)
+                    if hints:
+                        mem.wait_hint(c, s)
                     if counting:
                         cnt["prefetch_hits"] += 1
                 elif cl.touched[p]:
@@ -310,33 +403,52 @@ def run(trace, window: int, mem: PagedMemory | None = None,
             top, prob = predictor.predict(ids, k, vocab.oov, with_prob=True)
             top = top.cpu().numpy()
             prob = prob.cpu().numpy()
+            picks = []     # (client, page) in decision order
             for row, c in enumerate(want):
                 cl = clients[c]
                 last = int(clients[c].events[-1])
-                asked = []
+                chosen = set()
                 for tid, pr in zip(top[row], prob[row]):
                     if int(tid) >= vocab.n_known or pr < min_prob:
                         continue
                     q = last + int(vocab.delta_of[int(tid)])
                     if not (0 <= q < n) or q in cl.win or q in cl.pf or \
-                            not cl.touched[q]:
+                            not cl.touched[q] or q in chosen:
                         continue
-                    asked.append(q)
+                    chosen.add(q)
+                    picks.append((c, q))
+            if hints:
+                # slots first, then one hint call for the whole step
+                slots = [mem.alloc(c) for c, _ in picks]
+                took = mem.hint([(c, q, s) for (c, q), s in
+                                 zip(picks, slots)])
+                for (c, _), s, ok in zip(picks, slots, took):
+                    if not ok:
+                        mem.release(c, s)
+                        if counting:
+                            cnt["prefetch_dropped"] += 1
+            else:
+                slots = [None] * len(picks)
+                took = [True] * len(picks)
+            for (c, q), s, ok in zip(picks, slots, took):
+                if not ok:
+                    continue
+                cl = clients[c]
+                if not hints:
                     s = mem.alloc(c) if mem is not None else 0
                     if mem is not None:
                         mem.decrypt(c, q, s)
-                    cl.pf[q] = s
+                cl.pf[q] = s
+                decisions.setdefault((c, t), []).append(q)
+                if counting:
+                    cnt["prefetch_issued"] += 1
+                    cnt["decrypts"] += 1
+                if len(cl.pf) > prefetch_slots:
+                    _, sd = cl.pf.popitem(last=False)
+                    if mem is not None:
+                        mem.release(c, sd)
                     if counting:
-                        cnt["prefetch_issued"] += 1
-                        cnt["decrypts"] += 1
-                    if len(cl.pf) > prefetch_slots:
-                        _, sd = cl.pf.popitem(last=False)
-                        if mem is not None:
-                            mem.release(c, sd)
-                        if counting:
-                            cnt["prefetch_wasted"] += 1
-                if asked:
-                    decisions[(c, t)] = asked
+                        cnt["prefetch_wasted"] += 1
     if mem is not None:
         mem.flush()
     return cnt, events, decisions, clients
@@ -346,6 +458,7 @@ def finish(mem: PagedMemory, clients) -> None:
     """Encrypt every page still in a window back into the store (the end of
     the run) unless a background encryption already stored it; unused
     prefetched pages are dropped."""
+    mem.wait_all_hints()
     for c, cl in enumerate(clients):
         for p, s in cl.win.items():
             if p not in cl.clean:  # clean pages are already stored

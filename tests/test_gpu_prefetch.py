@@ -144,3 +144,107 @@ def test_background_pre_encryption_store_bit_exact(threshold):
         _check_store(mem, tr, kb, tr.steps)
     finally:
         eng.close()
+
+
+def _trained(tr, W, split, steps=300, seed=24):
+    from paper_2004_09252_amd import prefetch
+    from paper_2004_09252_amd.predictor import Predictor
+    _, events, _, _ = prefetch.run(tr, W, stop=split, record_events=True)
+    vocab = prefetch.DeltaVocab([d for ev in events for d in np.diff(ev)])
+    xs, ys = prefetch.training_examples(events, vocab, 16)
+    pred = Predictor(max_batch=1024, seed=seed)
+    prefetch.train(pred, xs, ys, steps=steps, batch=512, lr=2e-3, seed=seed)
+    return pred, vocab
+
+
+def test_predictor_gain_at_equal_budget_with_hints():
+    """What the trained network gains over decrypt-on-fault alone (sections
+    4.2-4.3), at an equal clear-page budget: a window of W + P pages against
+    a window of W pages plus P pre-decrypted pages, the pre-decryptions sent
+    as prefetch hints (ms_prefetch_hint) with the predictor's default
+    confidence gate.  The gated predictor must remove at least a quarter of
+    the decrypt faults, its total decrypt work must stay within 1.5 times
+    the baseline's, and both ciphertext stores must be the oracle's."""
+    _note("predictor gain at equal budget, hints")
+    from paper_2004_09252_amd import memshield as ms
+    from paper_2004_09252_amd import prefetch
+    tr = workloads.access_trace(seed=24, total_pages=16 * 1024,
+                                accesses=16 * 8000, clients=16)
+    kb = _keys(tr, 24)
+    W, P = 6, 8
+    split = int(tr.steps * 0.8)
+    pred, vocab = _trained(tr, W, split)
+    assert pred.min_prob == pred.DEFAULT_MIN_PROB == 0.1
+    eng = ms.Engine(0)
+    try:
+        keys = [eng.key_load(k) for k in kb]
+        base_mem = prefetch.PagedMemory(eng, keys, tr.pages_per_client,
+                                        slots=W + P + 24)
+        base, _, _, cl = prefetch.run(tr, W + P, mem=base_mem,
+                                      count_from=split)
+        prefetch.finish(base_mem, cl)
+        ref = _oracle_counts(tr, W + P, split, tr.steps)
+        for k, v in ref.items():
+            assert base[k] == v, k
+        _check_store(base_mem, tr, kb, tr.steps)
+        del base_mem
+        mem = prefetch.PagedMemory(eng, keys, tr.pages_per_client,
+                                   slots=W + P + 24)
+        got, _, dec, cl = prefetch.run(tr, W, mem=mem, prefetch_slots=P,
+                                       predictor=pred, vocab=vocab, k=8,
+                                       predict_from=split, count_from=split,
+                                       hints=True)
+        prefetch.finish(mem, cl)
+        ref = _oracle_counts(tr, W, split, tr.steps, decisions=dec, slots=P)
+        for k, v in ref.items():
+            assert got[k] == v, k
+        assert got["prefetch_dropped"] == 0
+        assert mem.hints_issued == got["prefetch_issued"] > 0
+        _check_store(mem, tr, kb, tr.steps)
+        print("baseline faults %d decrypts %d; predictor faults %d "
+              "decrypts %d hits %d issued %d" % (
+                  base["faults"], base["decrypts"], got["faults"],
+                  got["decrypts"], got["prefetch_hits"],
+                  got["prefetch_issued"]), flush=True)
+        assert got["faults"] <= 0.75 * base["faults"]
+        assert got["decrypts"] <= 1.5 * base["decrypts"]
+    finally:
+        eng.close()
+
+
+def test_hints_and_fused_prefetch_store_the_same():
+    """Pre-decryptions as prefetch hints on the engine's streams or inside
+    the fused demand launches: the same decisions, the same counters as the
+    oracle's replay, and bit-exact ciphertext stores."""
+    _note("hints vs fused pre-decryption")
+    from paper_2004_09252_amd import memshield as ms
+    from paper_2004_09252_amd import prefetch
+    tr = workloads.access_trace(seed=25, total_pages=16 * 256,
+                                accesses=16 * 3000, clients=16)
+    kb = _keys(tr, 25)
+    W, P = 6, 8
+    split = int(tr.steps * 0.6)
+    pred, vocab = _trained(tr, W, split, steps=150, seed=25)
+    eng = ms.Engine(0)
+    try:
+        keys = [eng.key_load(k) for k in kb]
+        out = []
+        for hints in (False, True):
+            mem = prefetch.PagedMemory(eng, keys, tr.pages_per_client,
+                                       slots=W + P + 24)
+            cnt, _, dec, cl = prefetch.run(
+                tr, W, mem=mem, prefetch_slots=P, predictor=pred,
+                vocab=vocab, k=8, predict_from=split, count_from=split,
+                min_prob=0.0, hints=hints)
+            prefetch.finish(mem, cl)
+            ref = _oracle_counts(tr, W, split, tr.steps, decisions=dec,
+                                 slots=P)
+            for k, v in ref.items():
+                assert cnt[k] == v, (hints, k)
+            _check_store(mem, tr, kb, tr.steps)
+            out.append((cnt, dec))
+            del mem
+        assert out[0][1] == out[1][1]
+        assert out[0][0] == out[1][0]
+    finally:
+        eng.close()
