@@ -83,23 +83,42 @@ def read_traffic():
         return None
 
 
-def cpu_baseline(b, n_pages_sample: int, reps: int):
+def _cpu_quota():
+    """CPUs the cgroup lets this process use (cpu.max), or None."""
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        return None if q == "max" else round(int(q) / int(per), 2)
+    except (OSError, ValueError):
+        return None
+
+
+def cpu_baseline(b, n_pages_sample: int, runs: int, reps: int):
+    """The scalar C oracle on every host CPU this process may run on
+    (len(os.sched_getaffinity(0)) threads): `runs` timed runs of `reps`
+    encrypt + decrypt passes over the first n_pages_sample pages; the median
+    run is reported, with the spread."""
     import numpy as np
     import oracle
-    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    threads = max(1, len(os.sched_getaffinity(0)))
     data = b.data[:n_pages_sample]
     nonces = oracle.nonces_linear(n_pages_sample, b.nonce_base,
                                   b.nonce_stride, b.nonce_tag)
     used = threads
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        enc, used = oracle.cipher_pages_timed(b.key, nonces, data,
-                                              threads=threads)
-        dec, used = oracle.cipher_pages_timed(b.key, nonces, enc,
-                                              threads=threads)
-    dt = time.perf_counter() - t0
+    rates = []
+    t_all = time.perf_counter()
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            enc, used = oracle.cipher_pages_timed(b.key, nonces, data,
+                                                  threads=threads)
+            dec, used = oracle.cipher_pages_timed(b.key, nonces, enc,
+                                                  threads=threads)
+        dt = time.perf_counter() - t0
+        rates.append(reps * 2 * n_pages_sample * 4096 / dt / 1e9)
+    wall = time.perf_counter() - t_all
     assert np.array_equal(dec, data)
-    gbs = reps * 2 * n_pages_sample * 4096 / dt / 1e9
+    rates.sort()
+    gbs = float(np.median(rates))
     # the same oracle on one thread, over the first 128 MiB
     n1 = min(n_pages_sample, 32768)
     t0 = time.perf_counter()
@@ -110,11 +129,15 @@ def cpu_baseline(b, n_pages_sample: int, reps: int):
     assert np.array_equal(dec1, data[:n1])
     return {"value": round(gbs, 4), "unit": "GB/s", "cores": int(used),
             "kind": "oracle",
-            "sample": "%d x (encrypt + decrypt) of the first %d pages "
-                      "(%d MiB) of the bulk workload, scalar C oracle, "
-                      "%d threads, %.1f s wall" % (
-                          reps, n_pages_sample, n_pages_sample // 256,
-                          used, dt),
+            "sample": "median of %d runs, each %d x (encrypt + decrypt) of "
+                      "the first %d pages (%d MiB) of the bulk workload, "
+                      "scalar C oracle, %d threads (all CPUs in the "
+                      "affinity mask), %.1f s wall" % (
+                          runs, reps, n_pages_sample, n_pages_sample // 256,
+                          used, wall),
+            "runs_GBps": [round(r, 3) for r in rates],
+            "affinity_cpus": len(os.sched_getaffinity(0)),
+            "cgroup_cpu_quota": _cpu_quota(),
             "single_thread": {
                 "GBps": round(2 * n1 * 4096 / dt1 / 1e9, 4),
                 "sample": "encrypt + decrypt of the first %d pages (%d MiB), "
@@ -129,28 +152,37 @@ def run_bulk(args, ms, torch, b):
     ct = torch.empty_like(src)
     pt = torch.empty_like(src)
     nonce = ms.linear_nonce(b.nonce_base, b.nonce_stride, b.nonce_tag)
-    stream = torch.cuda.current_stream()
-
-    def step(evs=None):
-        if evs is not None:
-            evs[0].record(stream)
-        eng.encrypt_pages(key, src, ct, nonce, stream=stream)
-        if evs is not None:
-            evs[1].record(stream)
-        eng.decrypt_pages(key, ct, pt, nonce, stream=stream)
-        if evs is not None:
-            evs[2].record(stream)
-
-    for _ in range(args.warmup):
-        step()
+    # a stream of the bench's own: the launches and the events that time
+    # them are on it (torch's default stream is handle 0, which the engine
+    # reads as "the context's stream")
+    stream = torch.cuda.Stream()
     torch.cuda.synchronize()
-    if not torch.equal(pt, src):
-        raise RuntimeError("round trip failed")
-    # HIP events on the stream the kernels run on, around the whole timed
-    # region: the average launch duration is the GPU time per launch
-    # (back-to-back launches, so gaps between them are included).
+
+    def step():
+        eng.encrypt_pages(key, src, ct, nonce, stream=stream)
+        eng.decrypt_pages(key, ct, pt, nonce, stream=stream)
+
+    # Clock ramp.  The chip lowers its clock within tens of milliseconds of
+    # idling and then runs the next ~50 launches of this kernel slower
+    # (about 700 us falling to 480 us per 1 GiB launch on a traced run):
+    # the workload is generated on the host first, so the same steps run
+    # for ramp_seconds, and the warmup steps and the timed steps follow
+    # with no idle gap (only the synchronize of the timing bracket).
+    ramp_steps = 0
+    t_ramp = time.perf_counter()
+    while time.perf_counter() - t_ramp < args.ramp_seconds:
+        for _ in range(10):
+            step()
+        ramp_steps += 10
+        stream.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True)
+           for _ in range(2 * args.steps + 1)]
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(args.warmup):
+        step()
+    # the timed region: HIP events on the stream the kernels run on around
+    # the K steps (the average launch duration is that time over 2K)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
@@ -159,7 +191,21 @@ def run_bulk(args, ms, torch, b):
     e1.record(stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    launch_ms = [e0.elapsed_time(e1) / (2 * args.steps)]
+    avg_ms = e0.elapsed_time(e1) / (2 * args.steps)
+    # the same K steps again at once, with an event between every two
+    # launches, for the spread of single launches (an event record adds a
+    # few microseconds between launches, so these are not the average)
+    evs[0].record(stream)
+    for k in range(args.steps):
+        eng.encrypt_pages(key, src, ct, nonce, stream=stream)
+        evs[2 * k + 1].record(stream)
+        eng.decrypt_pages(key, ct, pt, nonce, stream=stream)
+        evs[2 * k + 2].record(stream)
+    torch.cuda.synchronize()
+    launch_ms = [evs[i].elapsed_time(evs[i + 1])
+                 for i in range(2 * args.steps)]
+    if not torch.equal(pt, src):
+        raise RuntimeError("round trip failed")
     # spot-check the last ciphertext against the oracle on a few pages
     import numpy as np
     import oracle
@@ -171,19 +217,29 @@ def run_bulk(args, ms, torch, b):
             for i in sample]), b.data[sample])
     if not np.array_equal(got, want):
         raise RuntimeError("ciphertext differs from the oracle")
+    # the kernel those launches ran, as the library reports it
+    st, info = ms.ms_plain_launch_info(eng.ctx, n, ms.MS_NONCE_LINEAR)
+    if st:
+        raise RuntimeError("ms_plain_launch_info: " + ms.ms_status_str(st))
+    launch = {"kernel": info.kernel.decode(), "grid_blocks": info.grid_blocks,
+              "block_threads": info.block_threads,
+              "waves_per_cu": info.waves_per_cu,
+              "launches_per_call": info.launches}
     eng.key_destroy(key)
     eng.close()
     del src, ct, pt
     torch.cuda.empty_cache()
-    return dt, launch_ms
+    return dt, avg_ms, launch_ms, ramp_steps, launch
 
 
 def run_variants(args, ms, torch, b):
-    """Reduced-round ChaCha (12 and 8 rounds) on the bulk workload: fewer
-    integer operations per byte move the kernel from the ALU roof toward
-    the HBM roof.  Each row: data GB/s of one encrypt pass, the ALU fraction
-    (rounds*48 + 32 operations per 64-byte block) and the HBM fraction
-    (2 bytes moved per data byte)."""
+    """The cipher variants on the bulk workload: ChaCha with 20, 12 and 8
+    rounds, and the second cipher, Salsa20, with 20, 12 and 8 rounds (the
+    same operation count per round).  Fewer integer operations per byte
+    move the kernel from the ALU roof toward the HBM roof.  Each row: data
+    GB/s of one encrypt pass, the ALU fraction (rounds*48 + 32 operations
+    per 64-byte block) and the HBM fraction (2 bytes moved per data
+    byte)."""
     import numpy as np
     import oracle
     n = b.data.shape[0]
@@ -193,8 +249,10 @@ def run_variants(args, ms, torch, b):
     stream = torch.cuda.current_stream()
     sample = [0, n // 3, n - 1]
     out = {}
-    for rounds in (20, 12, 8):
-        eng = ms.Engine(0, rounds=rounds)
+    for cipher, rounds in (("chacha", 20), ("chacha", 12), ("chacha", 8),
+                           ("salsa", 20), ("salsa", 12), ("salsa", 8)):
+        cid = ms.MS_CIPHER_SALSA if cipher == "salsa" else ms.MS_CIPHER_CHACHA
+        eng = ms.Engine(0, rounds=rounds, cipher=cid)
         key = eng.key_load(b.key)
         for _ in range(20):
             eng.encrypt_pages(key, src, dst, nonce, stream=stream)
@@ -210,12 +268,16 @@ def run_variants(args, ms, torch, b):
         want = oracle.cipher_pages(
             b.key, np.stack([np.frombuffer(oracle.nonce_linear(
                 i, b.nonce_base, b.nonce_stride, b.nonce_tag), np.uint8)
-                for i in sample]), b.data[sample], rounds=rounds)
+                for i in sample]), b.data[sample], rounds=rounds,
+            cipher=cipher)
         got = dst.view(n, 4096)[sample].cpu().numpy()
         if not np.array_equal(got, want):
-            raise RuntimeError("ChaCha%d differs from the oracle" % rounds)
+            raise RuntimeError("%s%d differs from the oracle" % (cipher,
+                                                                 rounds))
+        # both ciphers: rounds x 4 quarter rounds x 12 add/xor/rotate, plus
+        # 16 feed-forward adds and 16 data xors per 64-byte block
         ops = (rounds * 48 + 32) * 64.0 * n
-        out["chacha%d" % rounds] = {
+        out["%s%d" % (cipher, rounds)] = {
             "data_GBps": round(n * 4096 / t / 1e9, 1),
             "ms_per_GiB": round(t * 1e3, 4),
             "alu_frac": round(ops / t / MI355X_INT32_VALU_OPS, 4),
@@ -567,16 +629,21 @@ def run_serving(args, ms, torch):
                        "pages log-uniform, 64 clients, 8 GiB admission cap, "
                        "%d-page input pool" % (20000, args.serving_duration,
                                                lay.trace.n, pool_pages)}
+    # continuous batching on the launch stage needs a context of its own
+    eng_l = ms.Engine(0, serve_stage=ms.MS_SERVE_STAGE_LAUNCH)
+    keys_l = [eng_l.key_load(k) for k in w.keys]
     checked = 0
-    for name, mode in (("served_batched", ms.MS_SERVE_BATCHED),
-                       ("plain_per_request", ms.MS_SERVE_PLAIN),
-                       ("resident_ring", ms.MS_SERVE_RESIDENT)):
+    for name, mode, e, ks in (
+            ("served_batched", ms.MS_SERVE_BATCHED, eng, keys),
+            ("served_launch_stage", ms.MS_SERVE_BATCHED, eng_l, keys_l),
+            ("plain_per_request", ms.MS_SERVE_PLAIN, eng, keys),
+            ("resident_ring", ms.MS_SERVE_RESIDENT, eng, keys)):
         log("serving %s" % name)
         dst.zero_()
-        before = eng.stats()
-        res, lat = serving.run(eng, lay, keys, src, dst, mode)
+        before = e.stats()
+        res, lat = serving.run(e, lay, ks, src, dst, mode)
         r = serving.summarize(res)
-        after = eng.stats()
+        after = e.stats()
         if mode == ms.MS_SERVE_BATCHED:
             nb = after.batches - before.batches
             r["batches"] = int(nb)
@@ -594,6 +661,10 @@ def run_serving(args, ms, torch):
                 raise RuntimeError("serving output %d differs" % i)
             checked += 1
         r["sample_checked_vs_oracle"] = int(len(lay.sample))
+        if name == "served_batched":
+            r["stage"] = "ring (resident kernel, one descriptor per page)"
+        elif name == "served_launch_stage":
+            r["stage"] = "fused launches formed by the scheduler"
         out[name] = r
     # rate sweep: equal-p99 comparison
     sweep = []
@@ -604,11 +675,13 @@ def run_serving(args, ms, torch):
         ls = serving.layout(ws, ring_pages=ring, sample_every=0)
         ks = keys   # same 64 client keys
         row = {"rate_req_s": rate, "requests": int(ls.trace.n)}
-        for name, mode in (("served", ms.MS_SERVE_BATCHED),
-                           ("plain", ms.MS_SERVE_PLAIN),
-                           ("resident", ms.MS_SERVE_RESIDENT)):
+        for name, mode, e, kk in (
+                ("served", ms.MS_SERVE_BATCHED, eng, ks),
+                ("served_launch", ms.MS_SERVE_BATCHED, eng_l, keys_l),
+                ("plain", ms.MS_SERVE_PLAIN, eng, ks),
+                ("resident", ms.MS_SERVE_RESIDENT, eng, ks)):
             log("sweep %s %d req/s" % (name, rate))
-            res, _ = serving.run(eng, ls, ks, src, dst, mode)
+            res, _ = serving.run(e, ls, kk, src, dst, mode)
             row[name + "_GBps"] = round(res.data_gbps, 2)
             row[name + "_p50_us"] = round(res.p50_us, 1)
             row[name + "_p99_us"] = round(res.p99_us, 1)
@@ -618,7 +691,7 @@ def run_serving(args, ms, torch):
     table = []
     for bound in args.p99_bounds:
         row = {"p99_bound_us": bound}
-        for m in ("served", "plain", "resident"):
+        for m in ("served", "served_launch", "plain", "resident"):
             ok = [r[m + "_GBps"] for r in sweep if r[m + "_p99_us"] <= bound]
             row[m + "_GBps"] = max(ok) if ok else None
         table.append(row)
@@ -626,6 +699,9 @@ def run_serving(args, ms, torch):
     for k in keys:
         eng.key_destroy(k)
     eng.close()
+    for k in keys_l:
+        eng_l.key_destroy(k)
+    eng_l.close()
     del src, dst
     torch.cuda.empty_cache()
     return out
@@ -728,25 +804,37 @@ def run_prefetch(args, ms, torch):
                 return False
         return True
 
-    # background pre-encryption (encrypt-side twin of the prefetcher):
-    # threshold 4 of W+P = 16 window slots, alone and with the gated predictor
-    runs = (("baseline_window_W_plus_P", W + P, 0, False, 0.0, 0),
-            ("predictor_window_W_prefetch_P", W, P, True, 0.0, 0),
-            ("predictor_min_prob", W, P, True, args.prefetch_min_prob, 0),
-            ("background_pre_encryption", W + P, 0, False, 0.0, 4),
-            ("predictor_min_prob_and_background", W, P, True,
-             args.prefetch_min_prob, 4))
-    for name, window, slots, use, min_prob, bg in runs:
+    # runs at an equal clear-page budget (W + P): the baseline window; the
+    # predictor without its gate and with its default gate, pre-decrypting
+    # inside the fused demand launches (in program order) or as prefetch
+    # hints on the engine's streams; background pre-encryption (threshold 4
+    # of 16 window slots), alone and with the gated predictor's hints.
+    # Launches are timed on the device in the runs marked so, to show what
+    # the hints do to the demand launches beside them.
+    gate = args.prefetch_min_prob
+    runs = (("baseline_window_W_plus_P", W + P, 0, False, 0.0, 0, False,
+             True),
+            ("predictor_window_W_prefetch_P", W, P, True, 0.0, 0, False,
+             False),
+            ("predictor_min_prob", W, P, True, gate, 0, False, True),
+            ("predictor_min_prob_hints", W, P, True, gate, 0, True, True),
+            ("background_pre_encryption", W + P, 0, False, 0.0, 4, False,
+             False),
+            ("predictor_min_prob_and_background", W, P, True, gate, 4, True,
+             False))
+    for name, window, slots, use, min_prob, bg, hints, timed in runs:
         log("prefetch run: %s" % name)
         mem = prefetch.PagedMemory(eng, keys, tr.pages_per_client,
                                    slots=W + P + 32)
+        mem.time_flushes = timed
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         cnt, _, dec, cl = prefetch.run(
             tr, window, mem=mem, prefetch_slots=slots,
             predictor=pred if use else None, vocab=vocab if use else None,
-            k=8, predict_from=split, count_from=split, min_prob=min_prob,
-            bg_threshold=bg)
+            k=8, predict_from=split, count_from=split,
+            min_prob=min_prob if use else None, bg_threshold=bg,
+            hints=hints)
         prefetch.finish(mem, cl)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -755,9 +843,23 @@ def run_prefetch(args, ms, torch):
         if bg:
             r["bg_threshold"] = bg
         if use:
-            r["min_prob"] = min_prob
+            r["min_prob"] = pred.min_prob if min_prob is None else min_prob
+            r["pre_decrypt_path"] = ("ms_prefetch_hint" if hints else
+                                     "fused with demand launches")
             r["prefetch_precision"] = round(
                 cnt["prefetch_hits"] / max(cnt["prefetch_issued"], 1), 4)
+        if hints:
+            r["hints_issued"] = mem.hints_issued
+            r["hints_dropped"] = mem.hints_dropped
+            r["hint_waits"] = mem.hint_waits
+        if timed and mem.flush_events:
+            import numpy as np
+            d = np.array([a.elapsed_time(b) for a, b in mem.flush_events])
+            r["fused_launch_gpu_us"] = {
+                "launches": int(d.size),
+                "median": round(float(np.median(d)) * 1e3, 1),
+                "p99": round(float(np.percentile(d, 99)) * 1e3, 1),
+                "total_ms": round(float(d.sum()), 2)}
         r["seconds"] = round(dt, 2)
         r["fused_launches"] = mem.launches
         r["pages_through_gpu"] = mem.pages_moved
@@ -775,6 +877,7 @@ def run_prefetch(args, ms, torch):
             (r["encrypts"] + r["encrypts_bg"]) / max(base["encrypts"], 1), 3)
     b = base["faults"]
     for name in ("predictor_window_W_prefetch_P", "predictor_min_prob",
+                 "predictor_min_prob_hints",
                  "predictor_min_prob_and_background"):
         p = out[name]["faults"]
         out[name]["decrypt_faults_removed_frac"] = round(1 - p / max(b, 1), 4)
@@ -795,9 +898,15 @@ def main():
     ap.add_argument("--pages", type=int, default=262144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-pages", type=int, default=262144)
-    ap.add_argument("--cpu-reps", type=int, default=25,
-                    help="passes of the CPU oracle (25 x 2 GiB is about "
-                         "10 s on 16 host threads)")
+    ap.add_argument("--cpu-runs", type=int, default=5,
+                    help="timed runs of the CPU oracle (the median is "
+                         "reported)")
+    ap.add_argument("--cpu-reps", type=int, default=5,
+                    help="encrypt + decrypt passes per CPU run (5 x 2 GiB "
+                         "is about 2 s on 16 host threads)")
+    ap.add_argument("--ramp-seconds", type=float, default=0.5,
+                    help="untimed bulk steps before the warmup steps, so "
+                         "that the GPU clock has come up from idle")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-duration", type=float, default=10.0)
@@ -818,7 +927,9 @@ def main():
                          "JSON (for profiling that path alone)")
     ap.add_argument("--prefetch-window", type=int, default=8)
     ap.add_argument("--prefetch-train-steps", type=int, default=1500)
-    ap.add_argument("--prefetch-min-prob", type=float, default=0.1)
+    ap.add_argument("--prefetch-min-prob", type=float, default=None,
+                    help="confidence gate of the gated runs (default: the "
+                         "predictor's own, Predictor.DEFAULT_MIN_PROB)")
     ap.add_argument("--predictor-only", action="store_true",
                     help="time only the predictor's training steps and "
                          "predictions (one JSON object)")
@@ -851,11 +962,14 @@ def main():
         print(json.dumps(line), flush=True)
         return
     log("timing %d steps after %d warmup" % (args.steps, args.warmup))
-    dt, launch_ms = run_bulk(args, ms, torch, b)
+    dt, avg_ms, launch_ms, ramp_steps, launch = run_bulk(args, ms, torch, b)
     n = args.pages
     data_bytes = 2.0 * n * 4096 * args.steps
     value = data_bytes / dt / 1e9
-    avg_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
+    avg_launch_s = avg_ms / 1e3
+    srt = sorted(launch_ms)
+    min_launch_s = srt[0] / 1e3
+    med_launch_s = (srt[(len(srt) - 1) // 2] + srt[len(srt) // 2]) / 2e3
     ops = float(OPS_PER_PAGE) * n
     achieved_ops = ops / avg_launch_s
     traffic = read_traffic()
@@ -890,8 +1004,17 @@ def main():
                      "unit": "Tops/s",
                      "frac": round(achieved_ops / MI355X_INT32_VALU_OPS, 4),
                      "traffic": traffic,
-                     "kernel": "plain_pages_kernel<20 rounds, unroll 2, linear nonces>",
+                     "kernel": launch["kernel"],
+                     "launch": launch,
                      "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                     "min_launch_ms": round(min_launch_s * 1e3, 4),
+                     "median_launch_ms": round(med_launch_s * 1e3, 4),
+                     "frac_at_median_launch": round(
+                         ops / med_launch_s / MI355X_INT32_VALU_OPS, 4),
+                     "launches_timed": 2 * args.steps,
+                     "single_launch_spread": "min and median from a second "
+                     "pass of the same steps with an event between launches",
+                     "clock_ramp_steps": ramp_steps,
                      "ops_per_launch": ops,
                      "hbm_GBps_algorithmic": round(
                          HBM_BYTES_PER_PAGE * n / avg_launch_s / 1e9, 1),
@@ -919,7 +1042,8 @@ def main():
     if not args.no_cpu_baseline:
         sp = min(args.cpu_sample_pages, n)
         log("cpu baseline on %d pages" % sp)
-        line["cpu_baseline"] = cpu_baseline(b, sp, args.cpu_reps)
+        line["cpu_baseline"] = cpu_baseline(b, sp, args.cpu_runs,
+                                            args.cpu_reps)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

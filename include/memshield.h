@@ -129,7 +129,50 @@ typedef struct ms_config {
     uint32_t serve_spin_us;       /* the scheduler polls this long after its
                                      last work before it sleeps until the
                                      next submission (default 5000) */
+    uint32_t cipher;              /* MS_CIPHER_CHACHA (default, the paper's
+                                     cipher) or MS_CIPHER_SALSA (Salsa20,
+                                     see below); every page kernel of the
+                                     context uses it */
+    uint32_t serve_stage;         /* how ms_submit / ms_prefetch_hint run
+                                     their requests: MS_SERVE_STAGE_AUTO
+                                     (default), _LAUNCH or _RING, below */
 } ms_config;
+
+/*
+ * Serving stages.  MS_SERVE_STAGE_LAUNCH: a scheduler thread forms fused
+ * launches from the queued requests on the context's serving streams
+ * (continuous batching by launches).  MS_SERVE_STAGE_RING: requests of at
+ * most 1024 pages go to a resident kernel on an HSA queue of the context's
+ * own (the paper's never-ending kernel fed through memory mapped between
+ * host and device, section 4.4): the submitting thread writes one
+ * descriptor per page into a ring in pinned memory, the kernel's workers,
+ * one wave per position of their share, read each descriptor's key from
+ * the context's device key table, cipher the page and write a completion
+ * word that ms_poll reads directly; requests that arrive while others run
+ * are served at once by idle workers.  Longer requests still go to fused
+ * launches.  The kernel starts with the first submission (about one
+ * workgroup of 4 waves on every compute unit) and runs until ms_shutdown.
+ * Prefetch hints enter the ring only while no demand request waits and at
+ * most half of the workers hold work.  The ring runs ChaCha only.
+ * MS_SERVE_STAGE_AUTO: the ring for a ChaCha context, launches otherwise.
+ * ms_init returns MS_ENOTSUP for MS_SERVE_STAGE_RING with Salsa20.
+ */
+#define MS_SERVE_STAGE_AUTO 0u
+#define MS_SERVE_STAGE_LAUNCH 1u
+#define MS_SERVE_STAGE_RING 2u
+
+/*
+ * The context's stream cipher.  Sections 1 and 6 of the paper make the
+ * cipher a replaceable module; ChaCha (section 4.4) is the default.
+ * MS_CIPHER_SALSA is Salsa20 (Bernstein 2008) with `rounds` rounds over the
+ * same page interface: for page nonce N (12 bytes) block j of the page is
+ * the Salsa20 block with the 64-bit nonce N[0..7] and the 64-bit block
+ * counter LE32(N[8..11]) * 2^32 + j.  The resident-key engine
+ * (memshield_resident.h) runs ChaCha only: with a Salsa20 context it
+ * returns MS_ENOTSUP.
+ */
+#define MS_CIPHER_CHACHA 0u
+#define MS_CIPHER_SALSA 1u
 
 /* Tunables of the fused batched launch, chosen by ms_autotune. */
 typedef struct ms_tuning {
@@ -207,6 +250,26 @@ ms_status ms_encrypt_pages(ms_ctx *ctx, ms_key key, const void *src, void *dst,
 ms_status ms_decrypt_pages(ms_ctx *ctx, ms_key key, const void *src, void *dst,
                            uint64_t n_pages, const ms_nonce *nonce,
                            void *stream);
+
+/*
+ * What ms_encrypt_pages / ms_decrypt_pages launch for a call of n_pages
+ * pages with nonces of `nonce_kind` on this context: the kernel, named with
+ * its template arguments as a profiler prints it (cipher, rounds, pages in
+ * flight per wave, nonce kind), its grid and the number of launches.  For
+ * reports and profiles; it launches nothing.  Errors: MS_EINVAL.
+ */
+typedef struct ms_launch_info {
+    char kernel[96];          /* e.g. "plain_pages_kernel<0u, 20, 2, 1u>" */
+    uint32_t launches;        /* launches of one call (at most 2^24 pages
+                                 each) */
+    uint32_t grid_blocks;     /* workgroups of the first launch */
+    uint32_t block_threads;   /* threads per workgroup */
+    uint32_t waves_per_cu;    /* resident waves per compute unit */
+    uint32_t cipher, rounds, unroll, nonce_kind;
+} ms_launch_info;
+
+ms_status ms_plain_launch_info(ms_ctx *ctx, uint64_t n_pages,
+                               int32_t nonce_kind, ms_launch_info *out);
 
 /*
  * Run n requests, each with its own key, nonce and page count, as ONE fused

@@ -7,8 +7,10 @@
  * completion.  It exists in native code so that timing is not distorted by
  * the Python interpreter.  Two modes:
  *   MS_SERVE_BATCHED - client threads call ms_submit at each arrival; the
- *     engine's scheduler admits requests into fused launches (continuous
- *     batching); a poller thread observes completion with ms_poll;
+ *     context's serving stage runs them (continuous batching: fused
+ *     launches formed by the scheduler, or the ring of a resident kernel,
+ *     as ms_config.serve_stage says); a poller thread observes completion
+ *     with ms_poll;
  *   MS_SERVE_PLAIN - one dispatcher thread issues each request at its arrival
  *     as its own plain launch (ms_encrypt_pages) on one stream, records an
  *     event after it, and a poller observes the events in order: the
@@ -61,7 +63,10 @@ typedef struct ms_serve_result {
     uint64_t completed;
     uint64_t eagain_retries;   /* MS_EAGAIN answers that were retried */
     uint64_t failed;           /* requests that completed with an error */
-    uint64_t reserved[4];
+    uint64_t first_failed;     /* 1 + index of the first failed request,
+                                  0 if none */
+    int64_t first_failed_state;/* its completion state (an ms_status) */
+    uint64_t reserved[2];
 } ms_serve_result;
 
 /*

@@ -139,6 +139,97 @@ __device__ __forceinline__ void keystream(uint32_t (&o)[16],
   o[15] = x15 + n[2];
 }
 
+// ------------------------------------------------------------- Salsa20 ---
+// The second cipher behind the same page interface: Salsa20 (Bernstein,
+// 2008), ChaCha's predecessor.  Its state is
+//   [ c0 k0 k1 k2 | k3 c1 v0 v1 | t0 t1 c2 k4 | k5 k6 k7 c3 ]
+// with the sigma words c, the key words k, the 64-bit nonce v (page nonce
+// words 0, 1) and the 64-bit block counter t: t0 = the block index j (the
+// lane), t1 = page nonce word 2.  Its quarter round on (a, b, c, d) updates
+// b, c, d, a by xor with a rotated sum; a double round is a column round on
+// (0,4,8,12) (5,9,13,1) (10,14,2,6) (15,3,7,11) and a row round on
+// (0,1,2,3) (5,6,7,4) (10,11,8,9) (15,12,13,14).
+
+// Salsa20 quarter round on wave-uniform words (scalar unit).
+__device__ __forceinline__ void salsa_quarter_s(uint32_t& a, uint32_t& b,
+                                                uint32_t& c, uint32_t& d) {
+  b ^= srotl32<7>(a + d);
+  c ^= srotl32<9>(b + a);
+  d ^= srotl32<13>(c + b);
+  a ^= srotl32<18>(d + c);
+}
+
+#define MS_SALSA_QUARTER(a, b, c, d)                                  \
+  b ^= rotl32(a + d, 7); c ^= rotl32(b + a, 9); d ^= rotl32(c + b, 13); \
+  a ^= rotl32(d + c, 18);
+
+// Salsa20 keystream block `ctr` (the lane id), feed-forward included.  Only
+// word 8 depends on the lane at the start, so the first double round runs
+// five of its eight quarter rounds, and the uniform steps of the other
+// three, on the scalar unit.
+template <int ROUNDS>
+__device__ __forceinline__ void salsa_keystream(uint32_t (&o)[16],
+                                                const uint32_t (&key)[8],
+                                                const uint32_t (&nonce)[3],
+                                                uint32_t ctr) {
+  uint32_t k[8], n[3];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) k[i] = uni(key[i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) n[i] = uni(nonce[i]);
+  uint32_t x0 = kSigma0, x1 = k[0], x2 = k[1], x3 = k[2], x4 = k[3],
+           x5 = kSigma1, x6 = n[0], x7 = n[1], x8, x9 = n[2], x10 = kSigma2,
+           x11 = k[4], x12 = k[5], x13 = k[6], x14 = k[7], x15 = kSigma3;
+  // first column round: (0,4,8,12) meets the counter at its second step
+  x4 ^= srotl32<7>(x0 + x12);
+  x8 = ctr ^ srotl32<9>(x4 + x0);
+  x12 ^= rotl32(x8 + x4, 13);
+  x0 ^= rotl32(x12 + x8, 18);
+  salsa_quarter_s(x5, x9, x13, x1);
+  salsa_quarter_s(x10, x14, x2, x6);
+  salsa_quarter_s(x15, x3, x7, x11);
+  // first row round: (5,6,7,4) is still uniform; (10,11,8,9) and
+  // (15,12,13,14) start with uniform steps
+  MS_SALSA_QUARTER(x0, x1, x2, x3);
+  salsa_quarter_s(x5, x6, x7, x4);
+  x11 ^= srotl32<7>(x10 + x9);
+  x8 ^= srotl32<9>(x11 + x10);
+  x9 ^= rotl32(x8 + x11, 13);
+  x10 ^= rotl32(x9 + x8, 18);
+  x12 ^= srotl32<7>(x15 + x14);
+  x13 ^= rotl32(x12 + x15, 9);
+  x14 ^= rotl32(x13 + x12, 13);
+  x15 ^= rotl32(x14 + x13, 18);
+#pragma unroll
+  for (int r = 2; r < ROUNDS; r += 2) {
+    MS_SALSA_QUARTER(x0, x4, x8, x12);
+    MS_SALSA_QUARTER(x5, x9, x13, x1);
+    MS_SALSA_QUARTER(x10, x14, x2, x6);
+    MS_SALSA_QUARTER(x15, x3, x7, x11);
+    MS_SALSA_QUARTER(x0, x1, x2, x3);
+    MS_SALSA_QUARTER(x5, x6, x7, x4);
+    MS_SALSA_QUARTER(x10, x11, x8, x9);
+    MS_SALSA_QUARTER(x15, x12, x13, x14);
+  }
+  o[0] = x0 + kSigma0; o[1] = x1 + k[0]; o[2] = x2 + k[1]; o[3] = x3 + k[2];
+  o[4] = x4 + k[3]; o[5] = x5 + kSigma1; o[6] = x6 + n[0]; o[7] = x7 + n[1];
+  o[8] = x8 + ctr; o[9] = x9 + n[2]; o[10] = x10 + kSigma2;
+  o[11] = x11 + k[4]; o[12] = x12 + k[5]; o[13] = x13 + k[6];
+  o[14] = x14 + k[7]; o[15] = x15 + kSigma3;
+}
+
+// Keystream of the selected cipher.
+template <uint32_t CIPHER, int ROUNDS>
+__device__ __forceinline__ void cipher_keystream(uint32_t (&o)[16],
+                                                 const uint32_t (&key)[8],
+                                                 const uint32_t (&nonce)[3],
+                                                 uint32_t ctr) {
+  if constexpr (CIPHER == kCipherSalsa)
+    salsa_keystream<ROUNDS>(o, key, nonce, ctr);
+  else
+    keystream<ROUNDS>(o, key, nonce, ctr);
+}
+
 // Page data always lives in global memory; saying so lets the compiler use
 // global (not flat) loads and stores also where the pointers come from
 // descriptors.
@@ -179,12 +270,12 @@ __device__ __forceinline__ void load_page(uint4 (&v)[4], const PageJob& j,
 
 // Keystream for the page, transposed through LDS, XORed over the loaded
 // data and stored coalesced.
-template <int ROUNDS>
+template <int ROUNDS, uint32_t CIPHER = kCipherChaCha>
 __device__ __forceinline__ void cipher_page(uint4 (&v)[4], const PageJob& j,
                                             const uint32_t (&k)[8],
                                             uint4* lds, uint32_t lane) {
   uint32_t o[16];
-  keystream<ROUNDS>(o, k, j.n, lane);
+  cipher_keystream<CIPHER, ROUNDS>(o, k, j.n, lane);
 #pragma unroll
   for (int q = 0; q < 4; ++q)
     lds[lds_slot(lane * 4 + q)] =
@@ -208,7 +299,8 @@ __device__ __forceinline__ void cipher_page(uint4 (&v)[4], const PageJob& j,
 // no copies); UNROLL 1 loads, ciphers and stores one page at a time.  The
 // source also supplies each page's key (fixed for plain launches, looked up
 // in the key table per request for batches).
-template <int ROUNDS, int UNROLL, class PageSource>
+template <int ROUNDS, int UNROLL, uint32_t CIPHER = kCipherChaCha,
+          class PageSource>
 __device__ __forceinline__ void run_pages(PageSource& pages, uint4* lds,
                                           uint32_t lane) {
   PageJob ja, jb;
@@ -221,19 +313,19 @@ __device__ __forceinline__ void run_pages(PageSource& pages, uint4* lds,
       const bool more_b = pages.next(jb);
       if (more_b) load_page(b, jb, lane);
       pages.key(ja, k);
-      cipher_page<ROUNDS>(a, ja, k, lds, lane);
+      cipher_page<ROUNDS, CIPHER>(a, ja, k, lds, lane);
       if (!more_b) break;
       const bool more_a = pages.next(ja);
       if (more_a) load_page(a, ja, lane);
       pages.key(jb, k);
-      cipher_page<ROUNDS>(b, jb, k, lds, lane);
+      cipher_page<ROUNDS, CIPHER>(b, jb, k, lds, lane);
       if (!more_a) break;
     }
   } else {
     do {
       load_page(a, ja, lane);
       pages.key(ja, k);
-      cipher_page<ROUNDS>(a, ja, k, lds, lane);
+      cipher_page<ROUNDS, CIPHER>(a, ja, k, lds, lane);
     } while (pages.next(ja));
   }
 }

@@ -43,8 +43,16 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 constexpr uint32_t kMaxKeysLimit = 65536;
+// Ring serving stage: requests up to this many pages go to the ring (one
+// descriptor per page, so a request's pages run on as many workers at
+// once); longer ones, which are bound by bandwidth rather than latency, go
+// to the fused launches.
+constexpr uint64_t kRingMaxPages = 1024;
 static_assert(ms::kStaticBatchMaxRequests == MS_STATIC_BATCH_MAX_REQUESTS,
               "static batch limit");
+static_assert(ms::kCipherChaCha == MS_CIPHER_CHACHA &&
+                  ms::kCipherSalsa == MS_CIPHER_SALSA,
+              "cipher ids");
 
 inline bool hip_ok(hipError_t e) { return e == hipSuccess; }
 
@@ -93,6 +101,18 @@ struct Pending {
 struct TicketSlot {
   std::atomic<uint32_t> gen{0};
   std::atomic<int32_t> state{0};  // 0 pending, 1 done, <0 ms_status
+  // ring serving stage: the ring ticket once the request is published (0
+  // before), so that ms_poll can read its completion words itself
+  std::atomic<uint64_t> ring{0};
+};
+
+// A request published on the ring serving stage, not yet reaped.
+struct RingReq {
+  uint32_t ticket_slot;
+  uint32_t key_slot;
+  ms_ticket ring_ticket;
+  uint64_t bytes;
+  uint64_t desc;  // ring positions it holds
 };
 
 struct InflightBatch {
@@ -153,6 +173,9 @@ struct ms_ctx {
   std::condition_variable q_cv;
   std::deque<Pending> demand_q;
   std::deque<Pending> prefetch_q;
+  // ring serving stage: requests of at most kRingMaxPages pages
+  std::deque<Pending> ring_q;
+  std::deque<Pending> ring_pf_q;
   std::atomic<bool> stop{false};
   std::thread scheduler;
 
@@ -165,6 +188,19 @@ struct ms_ctx {
   std::vector<int> serve_free;
   std::deque<InflightBatch> inflight;
   uint64_t inflight_bytes = 0;  // under sched_mu (mirrored in stats)
+
+  // ring serving stage (serve_stage): a resident kernel on its own HSA
+  // queue reads each request's pages from a descriptor ring in mapped
+  // memory and writes a completion word per position.  Started at the first
+  // submission and kept until ms_shutdown; `ring` is written once (under
+  // sched_mu) and read without the lock by ms_poll.
+  bool ring_mode = false;
+  std::atomic<ms_resident*> ring{nullptr};
+  bool ring_failed = false;                 // (sched_mu)
+  std::vector<RingReq> ring_inflight;       // (sched_mu)
+  uint64_t ring_desc = 0;                   // positions held (sched_mu)
+  uint32_t ring_depth = 1u << 16;
+  uint32_t ring_workers = 0;
 
   std::atomic<int32_t> sticky_error{0};
 
@@ -472,7 +508,7 @@ ms_status get_graph(ms_ctx* c, BatchSlot& s, const Tuning& t, uint32_t grid,
   void* args[] = {(void*)&hdr, (void*)&keys, (void*)&ppw};
   hipKernelNodeParams kp;
   std::memset(&kp, 0, sizeof(kp));
-  kp.func = const_cast<void*>(ms::batch_kernel_fn(t.unroll, (int)c->cfg.rounds));
+  kp.func = const_cast<void*>(ms::batch_kernel_fn(t.unroll, c->cfg.cipher, (int)c->cfg.rounds));
   kp.gridDim = dim3(grid);
   kp.blockDim = dim3(ms::kBlockThreads);
   kp.sharedMemBytes = 0;
@@ -514,7 +550,8 @@ ms_status issue_slot(ms_ctx* c, BatchSlot& s, size_t copy_bytes,
                        stream);
     if (!hip_ok(e)) return dev_err(c, e);
     e = ms::launch_batch(reinterpret_cast<const ms::DevBatchHdr*>(s.dev),
-                         c->d_keys, t.ppw, t.unroll, grid, (int)c->cfg.rounds,
+                         c->d_keys, t.ppw, t.unroll, grid, c->cfg.cipher,
+                         (int)c->cfg.rounds,
                          stream);
     if (!hip_ok(e)) return dev_err(c, e);
   }
@@ -657,7 +694,8 @@ bool launch_one(ms_ctx* c) {
     const Tuning t = plain_tuning(c);
     hipError_t e = ms::launch_plain(
         a, r.nonce.kind == MS_NONCE_ARRAY ? ms::kNonceArray : ms::kNonceLinear,
-        (int)c->cfg.rounds, (uint32_t)c->cu_count * t.waves_per_cu, t.unroll,
+        c->cfg.cipher, (int)c->cfg.rounds,
+        (uint32_t)c->cu_count * t.waves_per_cu, t.unroll,
         strm);
     if (hip_ok(e)) e = hipEventRecord(s.done, strm);
     if (!hip_ok(e)) st = dev_err(c, e);
@@ -677,6 +715,153 @@ bool launch_one(ms_ctx* c) {
   return true;
 }
 
+// ------------------------------------------------------ ring serving ---
+
+// Start the ring at the first use (caller holds sched_mu).
+ms_status ensure_ring(ms_ctx* c) {
+  if (c->ring.load(std::memory_order_relaxed)) return MS_OK;
+  if (c->ring_failed) return MS_EDEVICE;
+  ms_resident_config rc;
+  ms_resident_config_default(&rc);
+  rc.workers = c->ring_workers;
+  rc.ring_depth = c->ring_depth;
+  rc.desc_pages = 1;
+  rc.idle_limit_ms = 0;  // runs until ms_shutdown
+  ms_resident* r = nullptr;
+  const ms_status st =
+      ms_internal_ring_start(c, &rc, c->d_keys, c->cfg.max_keys, &r);
+  if (st) {
+    c->ring_failed = true;
+    return st;
+  }
+  c->ring.store(r, std::memory_order_release);
+  return MS_OK;
+}
+
+void finish_ring_req(ms_ctx* c, const RingReq& q, int32_t state) {
+  c->key_refs[q.key_slot].fetch_sub(1);
+  {
+    std::lock_guard<std::mutex> lk(c->ticket_mu);
+    c->tickets[q.ticket_slot].state.store(state, std::memory_order_release);
+    c->tickets[q.ticket_slot].ring.store(0, std::memory_order_relaxed);
+    c->ticket_free.push_back(q.ticket_slot);
+  }
+  c->outstanding.fetch_sub(1);
+  c->st_completed.fetch_add(1);
+  c->inflight_bytes -= q.bytes;
+  c->st_inflight_bytes.store(c->inflight_bytes);
+  c->ring_desc -= q.desc;
+}
+
+// Mark finished ring requests complete; true when any was.
+bool ring_reap(ms_ctx* c) {
+  ms_resident* r = c->ring.load(std::memory_order_relaxed);
+  if (!r || c->ring_inflight.empty()) return false;
+  const bool gone = !ms_internal_ring_alive(r);
+  bool any = false;
+  size_t w = 0;
+  for (size_t i = 0; i < c->ring_inflight.size(); ++i) {
+    const RingReq q = c->ring_inflight[i];
+    const int d = ms_internal_ring_done(r, q.ring_ticket);
+    if (!d && !gone) {
+      c->ring_inflight[w++] = q;
+      continue;
+    }
+    if (!d) c->sticky_error.store(MS_EDEVICE);
+    finish_ring_req(c, q, d ? 1 : MS_EDEVICE);
+    any = true;
+  }
+  c->ring_inflight.resize(w);
+  return any;
+}
+
+// Move queued small requests onto the ring (caller holds sched_mu): demand
+// requests in arrival order while the admission cap and the ring's free
+// positions allow, prefetch hints only when no demand request waits and at
+// most half the workers hold work, so that a demand request never queues
+// behind hints.  True when any request was published or failed.
+bool ring_publish(ms_ctx* c) {
+  bool any = false;
+  if (ensure_ring(c) != MS_OK) {
+    // no ring: fail what is queued for it
+    std::deque<Pending> gone;
+    {
+      std::lock_guard<std::mutex> lk(c->q_mu);
+      gone.swap(c->ring_q);
+      for (auto& p : c->ring_pf_q) gone.push_back(p);
+      c->ring_pf_q.clear();
+    }
+    for (auto& p : gone)
+      complete_ticket_now(c, p.ticket_slot, MS_EDEVICE,
+                          (uint32_t)(p.req.key & 0xffffffffu) - 1);
+    return !gone.empty();
+  }
+  ms_resident* r = c->ring.load(std::memory_order_relaxed);
+  const uint64_t cap = c->cfg.admission_cap_bytes;
+  uint64_t published = 0, pages = 0, n_pf = 0;
+  for (;;) {
+    Pending p;
+    bool have = false, pf = false;
+    {
+      std::lock_guard<std::mutex> lk(c->q_mu);
+      std::deque<Pending>* q = nullptr;
+      if (!c->ring_q.empty()) {
+        q = &c->ring_q;
+      } else if (!c->ring_pf_q.empty() &&
+                 c->ring_desc < c->ring_workers / 2) {
+        q = &c->ring_pf_q;
+        pf = true;
+      }
+      if (q) {
+        const Pending& f = q->front();
+        const uint64_t b = f.req.n_pages * MS_PAGE_SIZE;
+        if (c->inflight_bytes + b <= cap &&
+            c->ring_desc + f.req.n_pages <= c->ring_depth) {
+          p = f;
+          q->pop_front();
+          have = true;
+        }
+      }
+    }
+    if (!have) break;
+    const uint32_t ks = (uint32_t)(p.req.key & 0xffffffffu) - 1;
+    ms_ticket rt = 0;
+    const ms_status st = ms_internal_ring_publish(
+        r, ks, p.req.src, p.req.dst, p.req.n_pages, p.req.nonce, &rt);
+    any = true;
+    if (st) {
+      // (MS_EAGAIN cannot happen: positions are counted until reaped)
+      if (st != MS_EAGAIN) c->sticky_error.store(MS_EDEVICE);
+      complete_ticket_now(c, p.ticket_slot, st == MS_EAGAIN ? MS_EDEVICE : st,
+                          ks);
+      continue;
+    }
+    c->tickets[p.ticket_slot].ring.store(rt, std::memory_order_release);
+    RingReq q;
+    q.ticket_slot = p.ticket_slot;
+    q.key_slot = ks;
+    q.ring_ticket = rt;
+    q.bytes = p.req.n_pages * MS_PAGE_SIZE;
+    q.desc = p.req.n_pages;
+    c->ring_inflight.push_back(q);
+    c->ring_desc += q.desc;
+    c->inflight_bytes += q.bytes;
+    ++published;
+    pages += p.req.n_pages;
+    n_pf += pf ? 1 : 0;
+  }
+  if (published) {
+    c->st_inflight_bytes.store(c->inflight_bytes);
+    if (c->inflight_bytes > c->st_max_inflight.load())
+      c->st_max_inflight.store(c->inflight_bytes);
+    if (published > c->st_max_batch.load()) c->st_max_batch.store(published);
+    c->st_batches.fetch_add(1);
+    c->st_pages.fetch_add(pages);
+    c->st_pf_issued.fetch_add(n_pf);
+  }
+  return any;
+}
+
 void scheduler_main(ms_ctx* c) {
   (void)hipSetDevice(c->device);
   auto last_work = Clock::now();
@@ -692,8 +877,12 @@ void scheduler_main(ms_ctx* c) {
     if (any) {
       std::lock_guard<std::mutex> lk(c->sched_mu);
       did = reap(c);
+      if (c->ring_mode) {
+        did = ring_reap(c) || did;
+        did = ring_publish(c) || did;
+      }
       while (launch_one(c)) did = true;
-      idle_device = c->inflight.empty();
+      idle_device = c->inflight.empty() && c->ring_inflight.empty();
     }
     if (did) {
       last_work = Clock::now();
@@ -701,7 +890,8 @@ void scheduler_main(ms_ctx* c) {
     }
     if (any) {
       std::lock_guard<std::mutex> lk(c->q_mu);
-      queues_empty = c->demand_q.empty() && c->prefetch_q.empty();
+      queues_empty = c->demand_q.empty() && c->prefetch_q.empty() &&
+                     c->ring_q.empty() && c->ring_pf_q.empty();
     }
     if (c->stop.load() && queues_empty && idle_device) break;
     if (!idle_device) {
@@ -727,7 +917,8 @@ void scheduler_main(ms_ctx* c) {
     std::unique_lock<std::mutex> lk(c->q_mu);
     c->q_cv.wait_for(lk, std::chrono::milliseconds(2), [c] {
       return c->stop.load() || c->outstanding.load() != 0 ||
-             !c->demand_q.empty() || !c->prefetch_q.empty();
+             !c->demand_q.empty() || !c->prefetch_q.empty() ||
+             !c->ring_q.empty() || !c->ring_pf_q.empty();
     });
   }
 }
@@ -778,7 +969,8 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
   }
   if (prefetch) {
     std::lock_guard<std::mutex> lk(c->q_mu);
-    if (c->prefetch_q.size() + n > c->cfg.prefetch_depth) {
+    if (c->prefetch_q.size() + c->ring_pf_q.size() + n >
+        c->cfg.prefetch_depth) {
       c->outstanding.fetch_sub(n);
       c->st_pf_dropped.fetch_add(n);
       if (tickets_out)
@@ -828,7 +1020,10 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
       p.req.key = (reqs[i].key & 0xffffffff00000000ull) | (ks[i] + 1);
       p.ticket_slot = ts[i];
       p.prefetch = prefetch;
-      (prefetch ? c->prefetch_q : c->demand_q).push_back(p);
+      if (c->ring_mode && reqs[i].n_pages <= kRingMaxPages)
+        (prefetch ? c->ring_pf_q : c->ring_q).push_back(p);
+      else
+        (prefetch ? c->prefetch_q : c->demand_q).push_back(p);
     }
   }
   if (!prefetch) {
@@ -837,12 +1032,16 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
     // which saves the hop to the scheduler thread at low load.  Under load
     // (batches in flight) requests queue and the scheduler batches them.
     // Completions are always reaped by the scheduler.
+    // On the ring stage the submitting thread publishes its small
+    // requests itself whenever the lock is free: a publication is a few
+    // stores into mapped memory.
     std::unique_lock<std::mutex> lk(c->sched_mu, std::try_to_lock);
-    if (lk.owns_lock() && c->inflight.empty()) {
+    if (lk.owns_lock() && (c->ring_mode || c->inflight.empty())) {
       int prev = c->device;
       (void)hipGetDevice(&prev);
       if (prev != c->device) (void)hipSetDevice(c->device);
-      (void)launch_one(c);
+      if (c->ring_mode) (void)ring_publish(c);
+      if (c->inflight.empty()) (void)launch_one(c);
       if (prev != c->device) (void)hipSetDevice(prev);
     }
   }
@@ -873,7 +1072,8 @@ ms_status launch_plain_run(ms_ctx* c, uint32_t slot, const void* src,
       nonce.kind == MS_NONCE_ARRAY ? ms::kNonceArray : ms::kNonceLinear;
   const Tuning t = plain_tuning(c);
   const uint32_t resident = (uint32_t)c->cu_count * t.waves_per_cu;
-  return dev_err(c, ms::launch_plain(a, kind, (int)c->cfg.rounds,
+  return dev_err(c, ms::launch_plain(a, kind, c->cfg.cipher,
+                                     (int)c->cfg.rounds,
                                      max_waves && max_waves < resident
                                          ? max_waves
                                          : resident,
@@ -976,6 +1176,12 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
   if (cfg.max_keys == 0 || cfg.max_keys > kMaxKeysLimit) return MS_EINVAL;
   if (cfg.rounds != 20 && cfg.rounds != 12 && cfg.rounds != 8)
     return MS_EINVAL;
+  if (cfg.cipher != MS_CIPHER_CHACHA && cfg.cipher != MS_CIPHER_SALSA)
+    return MS_EINVAL;
+  if (cfg.serve_stage > MS_SERVE_STAGE_RING) return MS_EINVAL;
+  // the ring's kernel runs ChaCha only
+  if (cfg.serve_stage == MS_SERVE_STAGE_RING && cfg.cipher != MS_CIPHER_CHACHA)
+    return MS_ENOTSUP;
   if (cfg.queue_depth == 0 || (cfg.queue_depth & (cfg.queue_depth - 1)) ||
       cfg.queue_depth > (1u << 24))
     return MS_EINVAL;
@@ -1006,11 +1212,17 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
   }
   c->cu_count = prop.multiProcessorCount;
   c->arch = prop.gcnArchName;
+  c->ring_mode = cfg.serve_stage == MS_SERVE_STAGE_RING ||
+                 (cfg.serve_stage == MS_SERVE_STAGE_AUTO &&
+                  cfg.cipher == MS_CIPHER_CHACHA);
+  // one workgroup of 4 waves per compute unit: a poller and the workers
+  c->ring_workers = (uint32_t)c->cu_count * ms::kWavesPerBlock - 1;
   c->resident_plain_wpc = ms::resident_waves_per_cu(
-      ms::plain_kernel_fn(2, (int)cfg.rounds, ms::kNonceLinear));
+      ms::plain_kernel_fn(2, cfg.cipher, (int)cfg.rounds, ms::kNonceLinear));
   for (uint32_t u = 1; u <= 2; ++u)
     c->resident_batch_wpc[u] =
-        ms::resident_waves_per_cu(ms::batch_kernel_fn(u, (int)cfg.rounds));
+        ms::resident_waves_per_cu(
+            ms::batch_kernel_fn(u, cfg.cipher, (int)cfg.rounds));
   ms_status st = MS_OK;
   const size_t key_bytes = (size_t)cfg.max_keys * MS_KEY_BYTES;
   if (!hip_ok(hipStreamCreate(&c->stream))) st = MS_EDEVICE;
@@ -1049,7 +1261,6 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
       c->static_slots.resize(MS_STATIC_BATCH_MAX_REQUESTS);
       c->static_ranges.reserve(MS_STATIC_BATCH_MAX_REQUESTS);
     }
-
     c->serve_slots.resize(cfg.inflight_batches);
     for (auto& s : c->serve_slots)
       if (!st) st = alloc_slot(s, cfg.max_batch_requests);
@@ -1092,6 +1303,8 @@ ms_status ms_shutdown(ms_ctx* c) {
   c->stop.store(true);
   c->q_cv.notify_all();
   if (c->scheduler.joinable()) c->scheduler.join();
+  // the serving ring's kernel ends once every published request is done
+  if (ms_resident* r = c->ring.exchange(nullptr)) ms_internal_ring_stop(r);
   (void)hipDeviceSynchronize();
   if (c->host) ms_internal_host_path_destroy(c->host);
   c->host = nullptr;
@@ -1170,6 +1383,37 @@ ms_status ms_decrypt_pages(ms_ctx* c, ms_key key, const void* src, void* dst,
   return plain_call(c, key, src, dst, n_pages, nonce, stream);
 }
 
+ms_status ms_plain_launch_info(ms_ctx* c, uint64_t n_pages,
+                               int32_t nonce_kind, ms_launch_info* out) {
+  if (!c || !out || n_pages == 0) return MS_EINVAL;
+  if (nonce_kind != MS_NONCE_ARRAY && nonce_kind != MS_NONCE_LINEAR)
+    return MS_EINVAL;
+  // the arithmetic of launch_plain_run and ms::launch_plain
+  const Tuning t = plain_tuning(c);
+  const uint64_t max_waves = (uint64_t)c->cu_count * t.waves_per_cu;
+  const uint64_t first =
+      n_pages < ms::kMaxPagesPerPlainLaunch ? n_pages
+                                            : ms::kMaxPagesPerPlainLaunch;
+  const uint64_t waves = first < max_waves ? first : max_waves;
+  std::memset(out, 0, sizeof(*out));
+  const uint32_t kind =
+      nonce_kind == MS_NONCE_ARRAY ? ms::kNonceArray : ms::kNonceLinear;
+  std::snprintf(out->kernel, sizeof(out->kernel),
+                "plain_pages_kernel<%uu, %u, %u, %uu>", c->cfg.cipher,
+                c->cfg.rounds, t.unroll, kind);
+  out->launches = (uint32_t)((n_pages + ms::kMaxPagesPerPlainLaunch - 1) /
+                             ms::kMaxPagesPerPlainLaunch);
+  out->grid_blocks =
+      (uint32_t)((waves + ms::kWavesPerBlock - 1) / ms::kWavesPerBlock);
+  out->block_threads = ms::kBlockThreads;
+  out->waves_per_cu = t.waves_per_cu;
+  out->cipher = c->cfg.cipher;
+  out->rounds = c->cfg.rounds;
+  out->unroll = t.unroll;
+  out->nonce_kind = (uint32_t)nonce_kind;
+  return MS_OK;
+}
+
 ms_status ms_process_batch(ms_ctx* c, const ms_request* reqs, size_t n,
                            void* stream) {
   if (!c) return MS_EINVAL;
@@ -1236,7 +1480,8 @@ ms_status ms_process_batch_static(ms_ctx* c, const ms_request* reqs,
                                 hipMemcpyHostToDevice, s);
   if (hip_ok(e))
     e = ms::launch_batch(static_cast<const ms::DevBatchHdr*>(c->d_static),
-                         c->d_keys, t.ppw, t.unroll, grid, (int)c->cfg.rounds,
+                         c->d_keys, t.ppw, t.unroll, grid, c->cfg.cipher,
+                         (int)c->cfg.rounds,
                          s);
   if (hip_ok(e)) e = hipEventRecord(c->static_done, s);
   if (!hip_ok(e)) return dev_err(c, e);
@@ -1273,7 +1518,14 @@ ms_status ms_poll(ms_ctx* c, const ms_ticket* t, size_t n, int32_t* done,
       const uint32_t s = (uint32_t)(t[i] & 0xffffffffu) - 1;
       const uint32_t g = (uint32_t)(t[i] >> 32);
       TicketSlot& ts = c->tickets[s];
-      const int32_t state = ts.state.load(std::memory_order_acquire);
+      int32_t state = ts.state.load(std::memory_order_acquire);
+      if (state == 0) {
+        // a request on the ring is done once its positions' completion
+        // words say so, before the scheduler reaps it
+        const ms_ticket rt = ts.ring.load(std::memory_order_acquire);
+        ms_resident* r = c->ring.load(std::memory_order_acquire);
+        if (rt && r && ms_internal_ring_done(r, rt)) state = 1;
+      }
       const uint32_t cur = ts.gen.load(std::memory_order_acquire);
       if (cur != g) {
         done[i] = 1;  // slot reused: this ticket completed long ago
@@ -1293,7 +1545,8 @@ ms_status ms_cancel_client(ms_ctx* c, uint32_t client, uint64_t* n_out) {
   std::vector<Pending> gone;
   {
     std::lock_guard<std::mutex> lk(c->q_mu);
-    for (auto* q : {&c->demand_q, &c->prefetch_q}) {
+    for (auto* q : {&c->demand_q, &c->prefetch_q, &c->ring_q,
+                    &c->ring_pf_q}) {
       std::deque<Pending> keep;
       for (auto& p : *q) {
         if (p.req.client == client) gone.push_back(p);
@@ -1416,7 +1669,8 @@ ms_status ms_autotune(ms_ctx* c, uint64_t n_pages, ms_tuning* out) {
             he = hipEventRecord(e0, c->stream);
             if (hip_ok(he))
               he = ms::launch_batch(hdr, c->d_keys, t.ppw, t.unroll, grid,
-                                    (int)c->cfg.rounds, c->stream);
+                                    c->cfg.cipher, (int)c->cfg.rounds,
+                                    c->stream);
             if (hip_ok(he)) he = hipEventRecord(e1, c->stream);
             if (hip_ok(he)) he = hipEventSynchronize(e1);
             float ms_ = 0;

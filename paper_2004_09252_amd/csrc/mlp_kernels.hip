@@ -1,10 +1,10 @@
 // Page-access predictor kernels for gfx950 (include/memshield_mlp.h).
 //
-// Matrix products use the bf16 matrix-core instruction
-// v_mfma_f32_16x16x16bf16_1k: a wave multiplies a 16x16 bf16 tile of A by a
-// 16x16 bf16 tile of B into a 16x16 float32 accumulator.  Operand layout for
-// lane l of the wave: A row (l % 16), K elements 4*(l/16)..+3; B column
-// (l % 16), K elements 4*(l/16)..+3; accumulator column (l % 16), rows
+// Matrix products use gfx950's bf16 matrix-core instruction
+// v_mfma_f32_16x16x32_bf16: a wave multiplies a 16x32 bf16 tile of A by a
+// 32x16 bf16 tile of B into a 16x16 float32 accumulator.  Operand layout for
+// lane l of the wave: A row (l % 16), K elements 8*(l/16)..+7; B column
+// (l % 16), K elements 8*(l/16)..+7; accumulator column (l % 16), rows
 // 4*(l/16)..+3.  A workgroup of four waves computes a 64x64 output tile,
 // each wave a 32x32 quarter (2x2 MFMA tiles), staging 64x128 bf16 tiles of A
 // and B through LDS per K step of 128: four 16-byte global loads per
@@ -29,7 +29,7 @@
 
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = ms::kGemmTile;
@@ -220,22 +220,23 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
     // the next step's global loads are in flight during this step's MFMAs
     if (k0 + kTileK < kend) fetch(k0 + kTileK);
 #pragma unroll
-    for (int kk = 0; kk < kTileK; kk += 16) {
-      const int kb = kk + 4 * (lane >> 4);
-      v4s a[2], b[2];
+    for (int kk = 0; kk < kTileK; kk += 32) {
+      // one 16-byte LDS read per operand tile: 8 consecutive K elements
+      const int kb = kk + 8 * (lane >> 4);
+      v8bf a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
-        a[i] = *reinterpret_cast<const v4s*>(
+        a[i] = *reinterpret_cast<const v8bf*>(
             &As[wm * 32 + i * 16 + (lane & 15)][kb]);
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        b[j] = *reinterpret_cast<const v4s*>(
+        b[j] = *reinterpret_cast<const v8bf*>(
             &Bt[wn * 32 + j * 16 + (lane & 15)][kb]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
               a[i], b[j], acc[i][j], 0, 0, 0);
     }
     lds_barrier();

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "memshield.h"
+#include "memshield_resident.h"
 
 struct HostPath;  // host-resident page state, defined in host_pages.cpp
 
@@ -61,3 +62,24 @@ ms_status ms_internal_copy_key(ms_ctx* c, ms_key key, void* dst,
 
 // Stops every resident-key engine of the context (resident.cpp).
 void ms_internal_resident_stop_all(ms_ctx* c);
+
+// The ring of the context's serving stage (resident.cpp): a resident kernel
+// that holds no key of its own and reads, for each descriptor, the row of
+// the context's device key table (`key_table`, `table_rows` rows) the
+// descriptor names.  Not registered with the context: its owner stops it
+// with ms_internal_ring_stop.  ChaCha only.
+ms_status ms_internal_ring_start(ms_ctx* c, const ms_resident_config* cfg,
+                                 const uint32_t* key_table,
+                                 uint32_t table_rows, ms_resident** out);
+// Publish one request (device pages, already validated) with key-table row
+// `key_row`; MS_EAGAIN while the ring slots it needs are busy, MS_ECLOSED
+// once the kernel has ended, MS_EDEVICE after a descriptor error.  The
+// ticket is polled with ms_resident_poll.
+ms_status ms_internal_ring_publish(ms_resident* r, uint32_t key_row,
+                                   const void* src, void* dst,
+                                   uint64_t n_pages, const ms_nonce& nonce,
+                                   ms_ticket* ticket_out);
+// 1 once every position of a ring ticket has completed, else 0.
+int ms_internal_ring_done(ms_resident* r, ms_ticket t);
+bool ms_internal_ring_alive(ms_resident* r);
+void ms_internal_ring_stop(ms_resident* r);

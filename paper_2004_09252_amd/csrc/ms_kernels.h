@@ -14,6 +14,9 @@ constexpr uint32_t kWavesPerBlock = kBlockThreads / kWave;
 
 enum NonceKind : uint32_t { kNonceArray = 0, kNonceLinear = 1 };
 
+// Stream cipher of the page kernels (the values of ms_config.cipher).
+enum CipherKind : uint32_t { kCipherChaCha = 0, kCipherSalsa = 1 };
+
 // One request of a fused batch, as the batch kernel reads it from device
 // memory.  64 bytes, so a wave fetches one with scalar loads.
 struct DevReq {
@@ -59,15 +62,22 @@ struct PlainArgs {
 // Plain launch: one wave per page up to `max_waves` waves, which then loop
 // over the remaining pages; `unroll` 2 overlaps a page's loads with the
 // previous page's cipher work, 1 does not.
-hipError_t launch_plain(const PlainArgs& a, uint32_t kind, int rounds,
-                        uint32_t max_waves, uint32_t unroll,
+// `cipher` is a CipherKind, `rounds` 20, 12 or 8.
+hipError_t launch_plain(const PlainArgs& a, uint32_t kind, uint32_t cipher,
+                        int rounds, uint32_t max_waves, uint32_t unroll,
                         hipStream_t stream);
 hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
                         uint32_t pages_per_wave, uint32_t unroll,
-                        uint32_t grid_blocks, int rounds, hipStream_t stream);
-// Kernel entry points (graph capture, occupancy queries).
-const void* batch_kernel_fn(uint32_t unroll, int rounds);
-const void* plain_kernel_fn(uint32_t unroll, int rounds, uint32_t kind);
+                        uint32_t grid_blocks, uint32_t cipher, int rounds,
+                        hipStream_t stream);
+// Kernel entry points (graph capture, occupancy queries); nullptr for a
+// combination that does not exist.
+const void* batch_kernel_fn(uint32_t unroll, uint32_t cipher, int rounds);
+const void* plain_kernel_fn(uint32_t unroll, uint32_t cipher, int rounds,
+                            uint32_t kind);
+// A plain launch covers at most this many pages (32-bit page counters in
+// the kernel); longer runs are split into several launches.
+constexpr uint64_t kMaxPagesPerPlainLaunch = 1ull << 24;
 // Waves of `fn` (256-thread workgroups) that fit on one compute unit at once;
 // 0 if the runtime cannot say.
 uint32_t resident_waves_per_cu(const void* fn);

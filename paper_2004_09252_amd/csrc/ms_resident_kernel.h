@@ -68,10 +68,15 @@ struct RkArgs {
   uint32_t n_workers;     // worker waves (the poller is one more wave)
   uint32_t max_pages;     // pages per descriptor
   uint32_t n_keys;        // 1: the key stays in every worker's registers;
-                          // 2..kRkMaxKeys: a table in each workgroup's LDS
+                          // 2..kRkMaxKeys: a table in each workgroup's LDS;
+                          // 0: keys are rows of `key_table` (below)
   uint32_t inv_step;      // worker w serves the positions congruent to
                           // w * inv_step modulo n_workers
-  uint32_t pad;
+  uint32_t table_rows;    // n_keys == 0: rows of key_table
+  const uint32_t* key_table;  // n_keys == 0: a context's device key table
+                          // (8 words per row), read per descriptor with
+                          // system-scope loads; the host keeps a row live
+                          // while descriptors that name it are in flight
 };
 
 // Kernel entry points (plain C names in the separately built code object),

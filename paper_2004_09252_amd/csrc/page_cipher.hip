@@ -30,6 +30,11 @@
 //     ("unroll" 2), or one page at a time ("unroll" 1);
 //   * no matrix cores: the keystream is integer ALU work.
 //
+// The same kernels run a second cipher, Salsa20 (ChaCha's predecessor, the
+// paper's replaceable cipher of sections 1 and 6), chosen per context:
+// words 6, 7 of its state take the page nonce's words 0, 1, its 64-bit
+// block counter is (page nonce word 2, j); see cipher_core.h.
+//
 // The plain kernel takes one run of pages with one key and one nonce rule.
 // The batched kernel walks a flattened list of (request, page) items, each
 // request with its own key slot and nonce rule, taking `pages_per_wave`
@@ -95,7 +100,7 @@ struct PlainPages {
   }
 };
 
-template <int ROUNDS, int UNROLL, uint32_t KIND>
+template <uint32_t CIPHER, int ROUNDS, int UNROLL, uint32_t KIND>
 __global__ __launch_bounds__(kBlockThreads, UNROLL == 2 ? 7 : 8) void plain_pages_kernel(
     PlainArgs a) {
   __shared__ uint4 lds[kWavesPerBlock][256];
@@ -114,7 +119,7 @@ __global__ __launch_bounds__(kBlockThreads, UNROLL == 2 ? 7 : 8) void plain_page
   src.key_slot = a.key_slot;
   src.page = blockIdx.x * kWavesPerBlock + w;
   src.step = gridDim.x * kWavesPerBlock;
-  run_pages<ROUNDS, UNROLL>(src, lds[w], lane);
+  run_pages<ROUNDS, UNROLL, CIPHER>(src, lds[w], lane);
 }
 
 // -------------------------------------------------------------- batched ---
@@ -198,7 +203,7 @@ struct BatchStream {
   }
 };
 
-template <int ROUNDS, int UNROLL>
+template <uint32_t CIPHER, int ROUNDS, int UNROLL>
 __device__ __forceinline__ void batch_body(const DevBatchHdr* hdr,
                                            const DevReq* reqs,
                                            const uint32_t* keys,
@@ -216,18 +221,19 @@ __device__ __forceinline__ void batch_body(const DevBatchHdr* hdr,
   s.c0 = wave * pages_per_wave;
   if (s.c0 >= s.b.total) return;
   s.b.start_chunk(s.c0);
-  run_pages<ROUNDS, UNROLL>(s, lds, lane);
+  run_pages<ROUNDS, UNROLL, CIPHER>(s, lds, lane);
 }
 
 // Descriptors in device memory (copied there before the launch).
-template <int ROUNDS, int UNROLL>
+template <uint32_t CIPHER, int ROUNDS, int UNROLL>
 __global__ __launch_bounds__(kBlockThreads, UNROLL == 2 ? 7 : 8) void batch_pages_kernel(
     const DevBatchHdr* __restrict__ hdr, const uint32_t* __restrict__ keys,
     uint32_t pages_per_wave) {
   __shared__ uint4 lds[kWavesPerBlock][256];
   const uint32_t w = wave_in_block();
-  batch_body<ROUNDS, UNROLL>(hdr, reinterpret_cast<const DevReq*>(hdr + 1),
-                             keys, pages_per_wave, lds[w], w);
+  batch_body<CIPHER, ROUNDS, UNROLL>(
+      hdr, reinterpret_cast<const DevReq*>(hdr + 1), keys, pages_per_wave,
+      lds[w], w);
 }
 
 // --------------------------------------------------------------- probes ---
@@ -289,37 +295,79 @@ __global__ __launch_bounds__(kBlockThreads) void fill_u32_kernel(
     dst[i] = value;
 }
 
-template <int ROUNDS, int UNROLL>
-hipError_t launch_plain_ru(const PlainArgs& a, uint32_t kind, uint32_t grid,
-                           hipStream_t stream) {
-  if (kind == kNonceArray)
-    hipLaunchKernelGGL((plain_pages_kernel<ROUNDS, UNROLL, kNonceArray>),
-                       dim3(grid), dim3(kBlockThreads), 0, stream, a);
-  else
-    hipLaunchKernelGGL((plain_pages_kernel<ROUNDS, UNROLL, kNonceLinear>),
-                       dim3(grid), dim3(kBlockThreads), 0, stream, a);
-  return hipGetLastError();
+// Plain kernel for one (cipher, rounds, unroll, nonce kind).
+template <uint32_t CIPHER, int ROUNDS, int UNROLL>
+const void* plain_fn(uint32_t kind) {
+  return kind == kNonceArray
+             ? reinterpret_cast<const void*>(
+                   &plain_pages_kernel<CIPHER, ROUNDS, UNROLL, kNonceArray>)
+             : reinterpret_cast<const void*>(
+                   &plain_pages_kernel<CIPHER, ROUNDS, UNROLL, kNonceLinear>);
 }
 
-template <int ROUNDS>
-hipError_t launch_plain_r(const PlainArgs& a, uint32_t kind, uint32_t grid,
-                          uint32_t unroll, hipStream_t stream) {
-  return unroll == 2 ? launch_plain_ru<ROUNDS, 2>(a, kind, grid, stream)
-                     : launch_plain_ru<ROUNDS, 1>(a, kind, grid, stream);
+template <uint32_t CIPHER>
+const void* plain_fn_c(uint32_t unroll, int rounds, uint32_t kind) {
+  if (unroll == 2) {
+    switch (rounds) {
+      case 20: return plain_fn<CIPHER, 20, 2>(kind);
+      case 12: return plain_fn<CIPHER, 12, 2>(kind);
+      case 8: return plain_fn<CIPHER, 8, 2>(kind);
+    }
+  } else if (unroll == 1) {
+    switch (rounds) {
+      case 20: return plain_fn<CIPHER, 20, 1>(kind);
+      case 12: return plain_fn<CIPHER, 12, 1>(kind);
+      case 8: return plain_fn<CIPHER, 8, 1>(kind);
+    }
+  }
+  return nullptr;
+}
+
+template <uint32_t CIPHER>
+const void* batch_fn_c(uint32_t unroll, int rounds) {
+#define MS_BATCH_FN(R, U) \
+  reinterpret_cast<const void*>(&batch_pages_kernel<CIPHER, R, U>)
+  if (unroll == 2) {
+    switch (rounds) {
+      case 20: return MS_BATCH_FN(20, 2);
+      case 12: return MS_BATCH_FN(12, 2);
+      case 8: return MS_BATCH_FN(8, 2);
+    }
+  } else if (unroll == 1) {
+    switch (rounds) {
+      case 20: return MS_BATCH_FN(20, 1);
+      case 12: return MS_BATCH_FN(12, 1);
+      case 8: return MS_BATCH_FN(8, 1);
+    }
+  }
+#undef MS_BATCH_FN
+  return nullptr;
 }
 
 }  // namespace
 
-// A plain launch covers at most this many pages (32-bit page counters in the
-// kernel); longer runs are split into several launches.
-constexpr uint64_t kMaxPagesPerPlainLaunch = 1ull << 24;
+const void* plain_kernel_fn(uint32_t unroll, uint32_t cipher, int rounds,
+                            uint32_t kind) {
+  switch (cipher) {
+    case kCipherChaCha: return plain_fn_c<kCipherChaCha>(unroll, rounds, kind);
+    case kCipherSalsa: return plain_fn_c<kCipherSalsa>(unroll, rounds, kind);
+  }
+  return nullptr;
+}
 
-hipError_t launch_plain(const PlainArgs& a, uint32_t kind, int rounds,
-                        uint32_t max_waves, uint32_t unroll,
+const void* batch_kernel_fn(uint32_t unroll, uint32_t cipher, int rounds) {
+  switch (cipher) {
+    case kCipherChaCha: return batch_fn_c<kCipherChaCha>(unroll, rounds);
+    case kCipherSalsa: return batch_fn_c<kCipherSalsa>(unroll, rounds);
+  }
+  return nullptr;
+}
+
+hipError_t launch_plain(const PlainArgs& a, uint32_t kind, uint32_t cipher,
+                        int rounds, uint32_t max_waves, uint32_t unroll,
                         hipStream_t stream) {
-  if (max_waves == 0 || (unroll != 1 && unroll != 2))
-    return hipErrorInvalidValue;
-  if (rounds != 20 && rounds != 12 && rounds != 8) return hipErrorInvalidValue;
+  const void* fn = plain_kernel_fn(unroll, cipher, rounds, kind);
+  if (!fn || max_waves == 0) return hipErrorInvalidValue;
   for (uint64_t done = 0; done < a.n_pages;) {
     PlainArgs part = a;
     part.first_page = a.first_page + done;
@@ -330,38 +378,13 @@ hipError_t launch_plain(const PlainArgs& a, uint32_t kind, int rounds,
     const uint64_t waves = part.n_pages < max_waves ? part.n_pages : max_waves;
     const uint32_t grid =
         (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipError_t e = hipErrorInvalidValue;
-    switch (rounds) {
-      case 20: e = launch_plain_r<20>(part, kind, grid, unroll, stream); break;
-      case 12: e = launch_plain_r<12>(part, kind, grid, unroll, stream); break;
-      case 8: e = launch_plain_r<8>(part, kind, grid, unroll, stream); break;
-    }
+    void* args[] = {(void*)&part};
+    const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBlockThreads),
+                                         args, 0, stream);
     if (e != hipSuccess) return e;
     done += part.n_pages;
   }
   return hipSuccess;
-}
-
-const void* plain_kernel_fn(uint32_t unroll, int rounds, uint32_t kind) {
-#define MS_PLAIN_FN(R, U)                                                   \
-  (kind == kNonceArray                                                      \
-       ? reinterpret_cast<const void*>(&plain_pages_kernel<R, U, kNonceArray>) \
-       : reinterpret_cast<const void*>(&plain_pages_kernel<R, U, kNonceLinear>))
-  if (unroll == 2) {
-    switch (rounds) {
-      case 20: return MS_PLAIN_FN(20, 2);
-      case 12: return MS_PLAIN_FN(12, 2);
-      case 8: return MS_PLAIN_FN(8, 2);
-    }
-  } else if (unroll == 1) {
-    switch (rounds) {
-      case 20: return MS_PLAIN_FN(20, 1);
-      case 12: return MS_PLAIN_FN(12, 1);
-      case 8: return MS_PLAIN_FN(8, 1);
-    }
-  }
-#undef MS_PLAIN_FN
-  return nullptr;
 }
 
 uint32_t resident_waves_per_cu(const void* fn) {
@@ -373,27 +396,11 @@ uint32_t resident_waves_per_cu(const void* fn) {
   return (uint32_t)blocks * kWavesPerBlock;
 }
 
-const void* batch_kernel_fn(uint32_t unroll, int rounds) {
-  if (unroll == 2) {
-    switch (rounds) {
-      case 20: return reinterpret_cast<const void*>(&batch_pages_kernel<20, 2>);
-      case 12: return reinterpret_cast<const void*>(&batch_pages_kernel<12, 2>);
-      case 8: return reinterpret_cast<const void*>(&batch_pages_kernel<8, 2>);
-    }
-  } else if (unroll == 1) {
-    switch (rounds) {
-      case 20: return reinterpret_cast<const void*>(&batch_pages_kernel<20, 1>);
-      case 12: return reinterpret_cast<const void*>(&batch_pages_kernel<12, 1>);
-      case 8: return reinterpret_cast<const void*>(&batch_pages_kernel<8, 1>);
-    }
-  }
-  return nullptr;
-}
-
 hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
                         uint32_t pages_per_wave, uint32_t unroll,
-                        uint32_t grid_blocks, int rounds, hipStream_t stream) {
-  const void* fn = batch_kernel_fn(unroll, rounds);
+                        uint32_t grid_blocks, uint32_t cipher, int rounds,
+                        hipStream_t stream) {
+  const void* fn = batch_kernel_fn(unroll, cipher, rounds);
   if (!fn || pages_per_wave == 0 || grid_blocks == 0)
     return hipErrorInvalidValue;
   void* args[] = {(void*)&batch, (void*)&keys, (void*)&pages_per_wave};

@@ -324,16 +324,27 @@ namespace {
 
 // Start an engine with n_keys keys: from `key_bytes` (32 bytes, n_keys == 1),
 // from the OS CSPRNG (both null, n_keys == 1), or copied device to device
-// from the context's key table (`handles`).
+// from the context's key table (`handles`).  With `table` (n_keys == 0) the
+// engine holds no key: descriptors name rows of that device key table.  An
+// engine started for the caller is registered with its context (stopped by
+// ms_shutdown); one the context starts for itself (`registered` false) is
+// the context's own to stop.
 ms_status start_engine(ms_ctx* c, const ms_resident_config* cfg_in,
                        const uint8_t* key_bytes, const ms_key* handles,
-                       uint32_t n_keys, ms_resident** out) {
-  if (!c || !out || n_keys == 0 || n_keys > ms::kRkMaxKeys) return MS_EINVAL;
+                       uint32_t n_keys, ms_resident** out,
+                       const uint32_t* table = nullptr,
+                       uint32_t table_rows = 0, bool registered = true) {
+  if (!c || !out) return MS_EINVAL;
+  if (table ? (n_keys != 0 || table_rows == 0)
+            : (n_keys == 0 || n_keys > ms::kRkMaxKeys))
+    return MS_EINVAL;
   ms_status st = ms_internal_sticky(c);
   if (st) return st;
   ms_resident_config cfg;
   if (cfg_in) cfg = *cfg_in; else ms_resident_config_default(&cfg);
   const int rounds = (int)ms_internal_config(c).rounds;
+  // the resident kernel holds the ChaCha rounds only
+  if (ms_internal_config(c).cipher != MS_CIPHER_CHACHA) return MS_ENOTSUP;
   if (cfg.ring_depth < 16 || cfg.ring_depth > (1u << 20) ||
       (cfg.ring_depth & (cfg.ring_depth - 1)) || cfg.desc_pages == 0 ||
       cfg.desc_pages > 1024 || cfg.idle_limit_ms > 3600u * 1000u)
@@ -359,7 +370,7 @@ ms_status start_engine(ms_ctx* c, const ms_resident_config* cfg_in,
   r->workers = cfg.workers;
   r->n_keys = n_keys;
   const size_t depth = cfg.ring_depth;
-  const size_t key_bytes_total = (size_t)n_keys * MS_KEY_BYTES;
+  const size_t key_bytes_total = (size_t)(table ? 1 : n_keys) * MS_KEY_BYTES;
   bool ok = hip_ok(hipStreamCreateWithFlags(&r->aux, hipStreamNonBlocking));
   if (!ok) {
     (void)hipGetLastError();
@@ -395,7 +406,15 @@ ms_status start_engine(ms_ctx* c, const ms_resident_config* cfg_in,
     release(r);
     return ms_internal_dev_err(c, e);
   }
-  if (handles) {
+  if (table) {
+    // no key of its own: the device buffer stays zero
+    e = hipMemsetAsync(r->key_buf, 0, key_bytes_total, r->aux);
+    if (hip_ok(e)) e = hipStreamSynchronize(r->aux);
+    if (!hip_ok(e)) {
+      release(r);
+      return ms_internal_dev_err(c, e);
+    }
+  } else if (handles) {
     // keys already on the device: copied from the context's key table, never
     // through host memory
     for (uint32_t i = 0; i < n_keys && !st; ++i)
@@ -442,6 +461,8 @@ ms_status start_engine(ms_ctx* c, const ms_resident_config* cfg_in,
   a.max_pages = cfg.desc_pages;
   a.n_keys = n_keys;
   a.inv_step = ms::share_stride_inverse(r->workers);
+  a.table_rows = table_rows;
+  a.key_table = table;
   st = dispatch(r, a, rounds);
   if (st) {
     release(r);
@@ -456,7 +477,7 @@ ms_status start_engine(ms_ctx* c, const ms_resident_config* cfg_in,
     }
     std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
-  {
+  if (registered) {
     std::lock_guard<std::mutex> lk(g_reg_mu);
     g_engines.emplace(c, r);
   }
@@ -465,6 +486,83 @@ ms_status start_engine(ms_ctx* c, const ms_resident_config* cfg_in,
 }
 
 }  // namespace
+
+ms_status ms_internal_ring_start(ms_ctx* c, const ms_resident_config* cfg,
+                                 const uint32_t* key_table,
+                                 uint32_t table_rows, ms_resident** out) {
+  if (!key_table) return MS_EINVAL;
+  return start_engine(c, cfg, nullptr, nullptr, 0, out, key_table,
+                      table_rows, false);
+}
+
+ms_status ms_internal_ring_publish(ms_resident* r, uint32_t key_row,
+                                   const void* src, void* dst,
+                                   uint64_t n_pages, const ms_nonce& nonce,
+                                   ms_ticket* ticket_out) {
+  if (!r || n_pages == 0 || r->n_keys != 0) return MS_EINVAL;
+  const uint64_t per = r->cfg.desc_pages;
+  const uint64_t m = (n_pages + per - 1) / per;
+  const uint64_t depth = r->cfg.ring_depth;
+  if (m > depth) return MS_EINVAL;
+  if (load_acq(&r->hctl->error)) return MS_EDEVICE;
+  if (kernel_exited(r)) return MS_ECLOSED;
+  const uint64_t s = reinterpret_cast<uint64_t>(src);
+  const uint64_t d = reinterpret_cast<uint64_t>(dst);
+  const uint64_t na = reinterpret_cast<uint64_t>(nonce.array);
+  std::lock_guard<std::mutex> lk(r->mu);
+  const uint64_t p0 = r->next_pos.load(std::memory_order_relaxed);
+  for (uint64_t q = p0; q < p0 + m; ++q)
+    if (q >= depth && load_acq(&r->completed[q & (depth - 1)]) < q - depth + 1)
+      return MS_EAGAIN;
+  for (uint64_t i = 0; i < m; ++i) {
+    const uint64_t q = p0 + i;
+    const uint64_t first = i * per;
+    ms::RkDesc& x = r->ring[q & (depth - 1)];
+    x.src = s + first * MS_PAGE_SIZE;
+    x.dst = d + first * MS_PAGE_SIZE;
+    if (nonce.kind == MS_NONCE_ARRAY) {
+      x.nonce_base = na + first * MS_NONCE_BYTES;
+      x.nonce_stride = 0;
+      x.tag = 0;
+      x.kind = 0;
+    } else {
+      x.nonce_base = nonce.base + first * nonce.stride;
+      x.nonce_stride = nonce.stride;
+      x.tag = nonce.tag;
+      x.kind = 1;
+    }
+    x.n_pages = (uint32_t)(n_pages - first < per ? n_pages - first : per);
+    x.key = key_row;
+    x.seq = q;
+  }
+  store_rel(&r->hctl->published, p0 + m);
+  r->next_pos.store(p0 + m, std::memory_order_release);
+  *ticket_out = ((p0 + 1) << kTicketCountBits) | m;
+  return MS_OK;
+}
+
+int ms_internal_ring_done(ms_resident* r, ms_ticket t) {
+  const uint64_t depth = r->cfg.ring_depth;
+  const uint64_t m = t & ((1ull << kTicketCountBits) - 1);
+  const uint64_t p0 = (t >> kTicketCountBits) - 1;
+  // last position first: it was published last and usually finishes last,
+  // so a pending ticket costs one read of host memory the device writes
+  // (a forward scan would reread a request's finished positions on every
+  // poll, which under load made the scheduler's reaping grow with the
+  // number of requests in flight)
+  for (uint64_t q = p0 + m; q-- > p0;)
+    if (load_acq(&r->completed[q & (depth - 1)]) < q + 1) return 0;
+  return 1;
+}
+
+bool ms_internal_ring_alive(ms_resident* r) {
+  return r && r->launched && !kernel_exited(r) &&
+         !load_acq(&r->hctl->error);
+}
+
+void ms_internal_ring_stop(ms_resident* r) {
+  if (r) release(r);
+}
 
 extern "C" {
 

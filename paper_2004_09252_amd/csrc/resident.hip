@@ -14,6 +14,11 @@
 //     counts itself in, and the last worker zeroes the buffer and tells the
 //     host; from then on the key exists only in registers (no scratch: the
 //     kernel's resource usage is checked to be spill-free);
+//   * an engine that serves a context's own requests (its serving stage)
+//     holds no key of its own: a descriptor names a row of the context's
+//     device key table, which the worker reads with system-scope loads for
+//     each descriptor (the key then lives in HBM, as for the launch-per-call
+//     kernels, and a row may be reloaded between descriptors);
 //   * an engine may instead hold up to kRkMaxKeys keys (one per client, say):
 //     each workgroup copies them into a table in its LDS before its waves
 //     start, the last worker wipes the device buffer as above, and a worker
@@ -208,12 +213,18 @@ __device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
   const uint32_t kind = (uint32_t)(kk64 >> 32);
   const uint32_t n_pages = (uint32_t)pt;
   const uint32_t tag = (uint32_t)(pt >> 32);
+  const uint32_t key_limit = a.n_keys ? a.n_keys : a.table_rows;
   if (seq != pos || n_pages == 0 || n_pages > a.max_pages ||
-      key >= a.n_keys || kind > 1) {
+      key >= key_limit || kind > 1) {
     st_sys32(&a.hctl->error, 1u);
   } else {
     uint32_t kk[8];
-    if (a.n_keys > 1) {
+    if (a.n_keys == 0) {
+      // a row of the context's key table, fresh for every descriptor
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        kk[i] = uni(ld_sys32(a.key_table + (uint64_t)key * 8u + i));
+    } else if (a.n_keys > 1) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) kk[i] = uni(keytab[key * 8u + i]);
     } else {
@@ -244,7 +255,7 @@ template <int ROUNDS>
 __device__ void serve_ring(const RkArgs& a, const uint32_t* keytab,
                            uint4* lds, uint32_t lane, uint32_t worker) {
   uint32_t k[8];
-  if (a.n_keys == 1) {
+  if (a.n_keys == 1) {  // (0: key-table rows; 2..: the LDS table)
 #pragma unroll
     for (int i = 0; i < 8; ++i) k[i] = uni(ld_sys32(a.key_buf + i));
   } else {

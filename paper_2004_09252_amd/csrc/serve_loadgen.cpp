@@ -270,7 +270,13 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
     lat[i] = us_between(arrival(i), done_t[i]);
     if (done_t[i] > last) last = done_t[i];
     bytes += tr->n_pages[i] * MS_PAGE_SIZE;
-    if (state[i] != 1) res->failed++;
+    if (state[i] != 1) {
+      if (!res->failed) {
+        res->first_failed = i + 1;
+        res->first_failed_state = state[i];
+      }
+      res->failed++;
+    }
     res->late_submit_us_max = std::max(res->late_submit_us_max, late[i]);
   }
   if (lat_out) std::memcpy(lat_out, lat.data(), n * sizeof(double));

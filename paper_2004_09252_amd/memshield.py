@@ -79,7 +79,16 @@ class ms_config(ctypes.Structure):
                 ("host_chunk_pages", ctypes.c_uint32),
                 ("host_stage_slots", ctypes.c_uint32),
                 ("host_mapped_waves", ctypes.c_uint32),
-                ("serve_spin_us", ctypes.c_uint32)]
+                ("serve_spin_us", ctypes.c_uint32),
+                ("cipher", ctypes.c_uint32),
+                ("serve_stage", ctypes.c_uint32)]
+
+
+MS_CIPHER_CHACHA = 0
+MS_CIPHER_SALSA = 1
+MS_SERVE_STAGE_AUTO = 0
+MS_SERVE_STAGE_LAUNCH = 1
+MS_SERVE_STAGE_RING = 2
 
 
 class ms_resident_config(ctypes.Structure):
@@ -123,8 +132,16 @@ class ms_serve_result(ctypes.Structure):
         "wall_s", "data_gbps", "mean_us", "p50_us", "p90_us", "p99_us",
         "p999_us", "max_us", "late_submit_us_max")] + \
         [(n, ctypes.c_uint64) for n in ("completed", "eagain_retries",
-                                        "failed")] + \
-        [("reserved", ctypes.c_uint64 * 4)]
+                                        "failed", "first_failed")] + \
+        [("first_failed_state", ctypes.c_int64),
+         ("reserved", ctypes.c_uint64 * 2)]
+
+
+class ms_launch_info(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_char * 96)] + [
+        (n, ctypes.c_uint32) for n in (
+            "launches", "grid_blocks", "block_threads", "waves_per_cu",
+            "cipher", "rounds", "unroll", "nonce_kind")]
 
 
 class ms_mlp_shape(ctypes.Structure):
@@ -154,6 +171,8 @@ _SIGS = {
                          _I32),
     "ms_process_batch": ([_P, ctypes.POINTER(ms_request), ctypes.c_size_t, _P],
                          _I32),
+    "ms_plain_launch_info": ([_P, _U64, _I32, ctypes.POINTER(ms_launch_info)],
+                             _I32),
     "ms_process_batch_static": ([_P, ctypes.POINTER(ms_request),
                                  ctypes.c_size_t, _P], _I32),
     "ms_submit": ([_P, ctypes.POINTER(ms_request), ctypes.c_size_t,
@@ -298,6 +317,13 @@ def _req_array(reqs):
         return reqs, len(reqs)
     arr = (ms_request * len(reqs))(*reqs)
     return arr, len(reqs)
+
+
+def ms_plain_launch_info(ctx, n_pages: int, nonce_kind: int):
+    info = ms_launch_info()
+    st = _L().ms_plain_launch_info(ctx, n_pages, nonce_kind,
+                                   ctypes.byref(info))
+    return st, info
 
 
 def ms_process_batch(ctx, reqs, stream=None) -> int:

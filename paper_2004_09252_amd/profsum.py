@@ -35,8 +35,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = [os.path.join(HERE, "csrc", f)
                   for f in ("page_cipher.hip", "cipher_core.h")]
 COPY_BYTES = 1 << 30
-BULK_KERNEL = "plain_pages_kernel<20, 2, 1u>"
+# ChaCha (cipher 0), 20 rounds, unroll 2, linear nonces
+BULK_KERNEL = "plain_pages_kernel<0u, 20, 2, 1u>"
 COPY_KERNEL = "copy_probe_kernel"
+PROBE_KERNEL = "valu_probe_kernel"
 N_XCD = 8   # GRBM_GUI_ACTIVE comes summed over the 8 XCDs of an MI355X
 
 
@@ -144,20 +146,26 @@ def valu(db_path: str, out_path: str, cmd: str) -> None:
     (GRBM_GUI_ACTIVE cycles over the dispatch duration)."""
     db = sqlite3.connect(db_path)
     vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    probe = collections.defaultdict(lambda: collections.defaultdict(list))
     for name, counter, value, dur in db.execute(
             "select kernel_name, counter_name, value, duration from "
             "counters_collection"):
         if BULK_KERNEL in name:
             vals[counter]["v"].append(value)
             vals[counter]["d"].append(dur)
+        elif PROBE_KERNEL in name:
+            probe[counter]["v"].append(value)
+            probe[counter]["d"].append(dur)
     pages = 262144
 
-    def avg(c):
-        v = vals[c]["v"]
+    def avg(c, v=vals):
+        v = v[c]["v"]
         return sum(v) / len(v) if v else float("nan")
 
     durs = vals["GRBM_GUI_ACTIVE"]["d"]
     dur = sum(durs) / len(durs) if durs else float("nan")
+    pdurs = probe["GRBM_GUI_ACTIVE"]["d"]
+    pdur = sum(pdurs) / len(pdurs) if pdurs else float("nan")
     lines = ["# VALU counters of the bulk plain page kernel (1 GiB pass, "
              "262144 pages)",
              "# command: " + cmd,
@@ -177,7 +185,18 @@ def valu(db_path: str, out_path: str, cmd: str) -> None:
              "valu_instr_rate_T_lane_ops: %.2f" % (
                  avg("SQ_INSTS_VALU") * 64 / dur / 1e3),
              "valu_peak_at_effective_clock_T: %.2f" % (
-                 256 * 64 * avg("GRBM_GUI_ACTIVE") / N_XCD / dur / 1e3)]
+                 256 * 64 * avg("GRBM_GUI_ACTIVE") / N_XCD / dur / 1e3),
+             "",
+             "# the VALU calibration probe (%s) in the same run: %d "
+             "dispatches" % (PROBE_KERNEL, len(probe["SQ_INSTS_VALU"]["v"])),
+             "probe_SQ_INSTS_VALU_per_dispatch: %.0f" % avg("SQ_INSTS_VALU",
+                                                           probe),
+             "probe_dispatch_duration_us: %.2f" % (pdur / 1e3),
+             "probe_valu_instr_rate_T_lane_ops: %.2f" % (
+                 avg("SQ_INSTS_VALU", probe) * 64 / pdur / 1e3),
+             "probe_effective_clock_GHz: %.3f" % (
+                 avg("GRBM_GUI_ACTIVE", probe) / N_XCD / pdur),
+             "probe_VALUBusy_percent: %.2f" % avg("VALUBusy", probe)]
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
 

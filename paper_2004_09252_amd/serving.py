@@ -100,6 +100,7 @@ def summarize(res) -> dict:
             "max_us": round(res.max_us, 1), "mean_us": round(res.mean_us, 1),
             "requests": int(res.completed), "wall_s": round(res.wall_s, 3),
             "eagain_retries": int(res.eagain_retries),
+            "failed": int(res.failed),
             "late_submit_us_max": round(res.late_submit_us_max, 1)}
 
 

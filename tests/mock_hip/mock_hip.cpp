@@ -139,7 +139,9 @@ hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int d) {
   std::memset(p, 0, sizeof(*p));
   std::strcpy(p->name, "mock");
   std::strcpy(p->gcnArchName, "gfx950-mock");
-  p->multiProcessorCount = 256;
+  // a smaller device for tests that run one host thread per wave
+  const char* cus = std::getenv("MOCK_HIP_CUS");
+  p->multiProcessorCount = cus ? std::atoi(cus) : 256;
   p->totalGlobalMem = (size_t)1 << 34;
   p->pciBusID = 0x42;  // the mock HSA agent carries the same address
   return hipSuccess;

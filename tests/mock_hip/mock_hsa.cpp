@@ -115,11 +115,19 @@ struct Model {
 
   void serve_one(const std::vector<uint8_t>& keys, uint64_t pos) {
     const ms::RkDesc d = a.ring[pos & a.ring_mask];
+    const uint32_t key_limit = a.n_keys ? a.n_keys : a.table_rows;
     if (d.seq != pos || d.n_pages == 0 || d.n_pages > a.max_pages ||
-        d.key >= a.n_keys || d.kind > 1) {
+        d.key >= key_limit || d.kind > 1) {
       store_rel(&a.hctl->error, 1u);
     } else {
+      uint8_t row[32];
       const uint8_t* k = keys.data() + (size_t)d.key * 32;
+      if (a.n_keys == 0) {
+        // a row of the context's key table, read for this descriptor
+        for (int i = 0; i < 8; ++i)
+          put_le32(row + 4 * i, a.key_table[(size_t)d.key * 8 + i]);
+        k = row;
+      }
       for (uint32_t p = 0; p < d.n_pages; ++p) {
         uint8_t n[12];
         if (d.kind == 0) {

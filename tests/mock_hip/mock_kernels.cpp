@@ -13,6 +13,9 @@
 extern "C" void oracle_cipher_page(const uint8_t key[32],
                                    const uint8_t nonce[12], int rounds,
                                    const uint8_t* in, uint8_t* out);
+extern "C" void oracle_salsa_cipher_page(const uint8_t key[32],
+                                         const uint8_t nonce[12], int rounds,
+                                         const uint8_t* in, uint8_t* out);
 
 namespace {
 
@@ -21,22 +24,24 @@ struct MockKernel {
   uint32_t unroll;
   int rounds;
   uint32_t kind;
+  uint32_t cipher;
 };
 
 int round_index(int rounds) { return rounds == 8 ? 0 : (rounds == 12 ? 1 : 2); }
 
-MockKernel g_plain[3][2][2];
-MockKernel g_batch[3][2];
+MockKernel g_plain[2][3][2][2];
+MockKernel g_batch[2][3][2];
 
 struct Init {
   Init() {
     const int rs[3] = {8, 12, 20};
-    for (int r = 0; r < 3; ++r)
-      for (uint32_t u = 0; u < 2; ++u) {
-        g_batch[r][u] = MockKernel{true, u + 1, rs[r], 0};
-        for (uint32_t k = 0; k < 2; ++k)
-          g_plain[r][u][k] = MockKernel{false, u + 1, rs[r], k};
-      }
+    for (uint32_t c = 0; c < 2; ++c)
+      for (int r = 0; r < 3; ++r)
+        for (uint32_t u = 0; u < 2; ++u) {
+          g_batch[c][r][u] = MockKernel{true, u + 1, rs[r], 0, c};
+          for (uint32_t k = 0; k < 2; ++k)
+            g_plain[c][r][u][k] = MockKernel{false, u + 1, rs[r], k, c};
+        }
   }
 } g_init;
 
@@ -53,7 +58,8 @@ void key_bytes(const uint32_t* keys, uint32_t slot, uint8_t out[32]) {
 
 void cipher(const uint8_t key[32], uint32_t kind, const uint32_t* nonce_array,
             uint64_t nonce_base, uint64_t nonce_stride, uint32_t tag,
-            uint64_t i, int rounds, const uint8_t* src, uint8_t* dst) {
+            uint64_t i, uint32_t which, int rounds, const uint8_t* src,
+            uint8_t* dst) {
   uint8_t n[12];
   if (kind == ms::kNonceArray) {
     for (int w = 0; w < 3; ++w) put_le32(n + 4 * w, nonce_array[i * 3 + w]);
@@ -63,11 +69,16 @@ void cipher(const uint8_t key[32], uint32_t kind, const uint32_t* nonce_array,
     put_le32(n + 4, (uint32_t)(v >> 32));
     put_le32(n + 8, tag);
   }
-  oracle_cipher_page(key, n, rounds, src + i * ms::kPageBytes,
-                     dst + i * ms::kPageBytes);
+  if (which == ms::kCipherSalsa)
+    oracle_salsa_cipher_page(key, n, rounds, src + i * ms::kPageBytes,
+                             dst + i * ms::kPageBytes);
+  else
+    oracle_cipher_page(key, n, rounds, src + i * ms::kPageBytes,
+                       dst + i * ms::kPageBytes);
 }
 
-void run_batch(const ms::DevBatchHdr* hdr, const uint32_t* keys, int rounds) {
+void run_batch(const ms::DevBatchHdr* hdr, const uint32_t* keys,
+               uint32_t which, int rounds) {
   const auto* reqs = reinterpret_cast<const ms::DevReq*>(hdr + 1);
   for (uint32_t r = 0; r < hdr->n_req; ++r) {
     const ms::DevReq& q = reqs[r];
@@ -75,7 +86,7 @@ void run_batch(const ms::DevBatchHdr* hdr, const uint32_t* keys, int rounds) {
     key_bytes(keys, q.key_slot, k);
     for (uint64_t i = 0; i < q.page_end - q.page_begin; ++i)
       cipher(k, q.kind, reinterpret_cast<const uint32_t*>(q.nonce), q.nonce,
-             q.stride, q.tag, i, rounds,
+             q.stride, q.tag, i, which, rounds,
              reinterpret_cast<const uint8_t*>(q.src),
              reinterpret_cast<uint8_t*>(q.dst));
   }
@@ -86,39 +97,44 @@ void run_batch(const ms::DevBatchHdr* hdr, const uint32_t* keys, int rounds) {
 void mock_run_batch_node(const void* func, const void* hdr,
                          const uint32_t* keys, uint32_t) {
   const auto* k = static_cast<const MockKernel*>(func);
-  run_batch(static_cast<const ms::DevBatchHdr*>(hdr), keys, k->rounds);
+  run_batch(static_cast<const ms::DevBatchHdr*>(hdr), keys, k->cipher,
+            k->rounds);
 }
 
 namespace ms {
 
-const void* batch_kernel_fn(uint32_t unroll, int rounds) {
-  return &g_batch[round_index(rounds)][unroll == 2 ? 1 : 0];
+const void* batch_kernel_fn(uint32_t unroll, uint32_t cipher, int rounds) {
+  return &g_batch[cipher ? 1 : 0][round_index(rounds)][unroll == 2 ? 1 : 0];
 }
-const void* plain_kernel_fn(uint32_t unroll, int rounds, uint32_t kind) {
-  return &g_plain[round_index(rounds)][unroll == 2 ? 1 : 0][kind ? 1 : 0];
+const void* plain_kernel_fn(uint32_t unroll, uint32_t cipher, int rounds,
+                            uint32_t kind) {
+  return &g_plain[cipher ? 1 : 0][round_index(rounds)][unroll == 2 ? 1 : 0]
+                 [kind ? 1 : 0];
 }
 uint32_t resident_waves_per_cu(const void*) { return 28; }
 
-hipError_t launch_plain(const PlainArgs& a, uint32_t kind, int rounds,
-                        uint32_t max_waves, uint32_t unroll,
+hipError_t launch_plain(const PlainArgs& a, uint32_t kind, uint32_t which,
+                        int rounds, uint32_t max_waves, uint32_t unroll,
                         hipStream_t stream) {
   if (max_waves == 0 || (unroll != 1 && unroll != 2)) return hipErrorInvalidValue;
   const PlainArgs x = a;
-  mock_enqueue(stream, [x, kind, rounds] {
+  mock_enqueue(stream, [x, kind, which, rounds] {
     uint8_t k[32];
     key_bytes(x.keys, x.key_slot, k);
     for (uint64_t i = 0; i < x.n_pages; ++i)
       cipher(k, kind, x.nonce_array, x.nonce_base, x.nonce_stride,
-             x.nonce_tag, x.first_page + i, rounds, x.src, x.dst);
+             x.nonce_tag, x.first_page + i, which, rounds, x.src, x.dst);
   });
   return hipSuccess;
 }
 
 hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
                         uint32_t, uint32_t unroll, uint32_t grid_blocks,
-                        int rounds, hipStream_t stream) {
+                        uint32_t which, int rounds, hipStream_t stream) {
   if (grid_blocks == 0 || (unroll != 1 && unroll != 2)) return hipErrorInvalidValue;
-  mock_enqueue(stream, [batch, keys, rounds] { run_batch(batch, keys, rounds); });
+  mock_enqueue(stream, [batch, keys, which, rounds] {
+    run_batch(batch, keys, which, rounds);
+  });
   return hipSuccess;
 }
 
@@ -157,3 +173,23 @@ __attribute__((weak)) void ms_internal_host_path_destroy(HostPath* h) {
   delete[] reinterpret_cast<char*>(h);
 }
 __attribute__((weak)) void ms_internal_resident_stop_all(ms_ctx*) {}
+__attribute__((weak)) ms_status ms_internal_ring_start(
+    ms_ctx*, const ms_resident_config*, const uint32_t*, uint32_t,
+    ms_resident**) {
+  return MS_ENOTSUP;
+}
+__attribute__((weak)) ms_status ms_internal_ring_publish(
+    ms_resident*, uint32_t, const void*, void*, uint64_t, const ms_nonce&,
+    ms_ticket*) {
+  return MS_ENOTSUP;
+}
+__attribute__((weak)) int ms_internal_ring_done(ms_resident*, ms_ticket) {
+  return 0;
+}
+__attribute__((weak)) bool ms_internal_ring_alive(ms_resident*) {
+  return false;
+}
+__attribute__((weak)) void ms_internal_ring_stop(ms_resident*) {}
+__attribute__((weak)) void ms_resident_config_default(ms_resident_config* c) {
+  std::memset(c, 0, sizeof(*c));
+}

@@ -67,6 +67,13 @@ int main() {
   cfg.inflight_batches = 3;
   cfg.prefetch_depth = 16;
   cfg.serve_spin_us = 300;
+#ifdef RING_STAGE
+  // the ring serving stage (resident kernel on the mock HSA runtime); a few
+  // requests above the ring's page limit still take the fused launches
+  cfg.serve_stage = MS_SERVE_STAGE_RING;
+#else
+  cfg.serve_stage = MS_SERVE_STAGE_LAUNCH;
+#endif
   ms_ctx* c = nullptr;
   CHECK(ms_init(&c, 0, &cfg));
 

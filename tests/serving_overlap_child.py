@@ -20,7 +20,8 @@ from paper_2004_09252_amd import workloads  # noqa: E402
 
 def main():
     import torch
-    eng = ms.Engine(0)  # the process's first streams are the engine's
+    # the process's first streams are the engine's; the launch stage
+    eng = ms.Engine(0, serve_stage=ms.MS_SERVE_STAGE_LAUNCH)
     rng = np.random.default_rng(42)
     kb = [rng.bytes(32) for _ in range(2)]
     keys = [eng.key_load(k) for k in kb]

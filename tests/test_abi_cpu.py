@@ -95,9 +95,9 @@ def test_headers_compile_as_c(tmp_path):
     # layout checks at compile time (a negative array size fails the build)
     c.write_text(incs +
                  'typedef char req_is_80[sizeof(ms_request) == 80 ? 1 : -1];\n'
-                 'typedef char cfg_is_56[sizeof(ms_config) == 56 ? 1 : -1];\n'
+                 'typedef char cfg_is_64[sizeof(ms_config) == 64 ? 1 : -1];\n'
                  'typedef char nonce_is_32[sizeof(ms_nonce) == 32 ? 1 : -1];\n'
-                 'int main(void){ ms_config c; req_is_80 a; cfg_is_56 b;'
+                 'int main(void){ ms_config c; req_is_80 a; cfg_is_64 b;'
                  ' nonce_is_32 d; (void)a; (void)b; (void)d;'
                  ' ms_config_default(&c); return 0; }\n')
     subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror",
@@ -111,7 +111,7 @@ def test_struct_layouts_match_binding():
     assert ctypes.sizeof(ms.ms_nonce) == 32
     assert ctypes.sizeof(ms.ms_request) == 80
     assert ctypes.sizeof(ms.ms_tuning) == 24
-    assert ctypes.sizeof(ms.ms_config) == 56
+    assert ctypes.sizeof(ms.ms_config) == 64
 
 
 @pytest.mark.parametrize("source,min_kernels", [("page_cipher.hip", 8),

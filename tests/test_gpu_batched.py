@@ -246,3 +246,33 @@ def test_autotune_returns_valid_tiling(ms, eng):
     assert t.waves_per_cu >= 1 and t.us_per_launch > 0
     st, t2 = ms.ms_get_tuning(eng.ctx, 4000)
     assert st == 0 and t2.pages_per_wave == t.pages_per_wave
+
+
+@pytest.mark.parametrize("rounds", [20, 8])
+def test_batched_salsa20_per_request(ms, rounds):
+    """The fused launch of a Salsa20 context: each request equals the
+    Salsa20 oracle run on that request alone."""
+    _note("batched salsa20 rounds=%d" % rounds)
+    import torch
+    e = ms.Engine(0, cipher=ms.MS_CIPHER_SALSA, rounds=rounds)
+    try:
+        w = _small(13, n_requests=60, max_pages=256)
+        nh = _linear_nonces(w)
+        keys = [e.key_load(k) for k in w.keys]
+        flat = np.concatenate([x.reshape(-1) for x in w.plain])
+        src = torch.from_numpy(flat).to("cuda")
+        dst = torch.zeros_like(src)
+        arr = _layout(ms, e, w, keys, src, dst)
+        e.process_batch(arr)
+        got = dst.cpu().numpy()
+        off = 0
+        for i, r in enumerate(w.requests):
+            n = r.n_pages * 4096
+            want = oracle.cipher_pages(w.keys[r.client], nh[i], w.plain[i],
+                                       rounds=rounds, cipher="salsa")
+            assert np.array_equal(got[off:off + n], want.reshape(-1)), i
+            off += n
+        for k in keys:
+            e.key_destroy(k)
+    finally:
+        e.close()

@@ -301,3 +301,108 @@ def test_reduced_round_variants(ms, rounds):
         assert np.array_equal(_host(dst).reshape(65, 4096), want)
     finally:
         e.close()
+
+
+@pytest.mark.parametrize("rounds", [20, 12, 8])
+@pytest.mark.parametrize("n_pages,in_place,kind", [
+    (1, False, "linear"), (63, True, "linear"), (257, False, "array"),
+    (4097, True, "array"), (3000, False, "linear")])
+def test_salsa20_pages_bit_exact(ms, rounds, n_pages, in_place, kind):
+    """The second cipher behind the same ABI (ms_config.cipher = Salsa20):
+    every page equals the Salsa20 oracle (nonce = page nonce bytes 0..7,
+    block counter = page nonce word 2 * 2^32 + j), and decrypting gives the
+    data back."""
+    _note("salsa20 rounds=%d n_pages=%d in_place=%s %s" % (
+        rounds, n_pages, in_place, kind))
+    import torch
+    e = ms.Engine(0, rounds=rounds, cipher=ms.MS_CIPHER_SALSA)
+    try:
+        rng = np.random.default_rng(5000 + rounds + n_pages)
+        data = workloads.random_pages(rng, n_pages)
+        kb = rng.bytes(32)
+        key = e.key_load(kb)
+        src = _dev(data)
+        dst = src if in_place else torch.zeros_like(src)
+        if kind == "array":
+            nonces = np.frombuffer(rng.bytes(12 * n_pages),
+                                   np.uint8).reshape(n_pages, 12)
+            nd = _dev(nonces)
+            nonce = ms.array_nonce(nd)
+        else:
+            base, stride, tag = 0x7F0000000000 + 4096 * 9, 4096, 0xDEADBEEF
+            nonces = oracle.nonces_linear(n_pages, base, stride, tag)
+            nonce = ms.linear_nonce(base, stride, tag)
+        e.encrypt_pages(key, src, dst, nonce)
+        got = _host(dst).reshape(n_pages, 4096)
+        want = oracle.cipher_pages(kb, nonces, data, rounds=rounds,
+                                   cipher="salsa", threads=HOST_THREADS)
+        assert np.array_equal(got, want)
+        back = torch.zeros_like(src)
+        e.decrypt_pages(key, dst, back, nonce)
+        assert np.array_equal(_host(back).reshape(n_pages, 4096), data)
+        e.key_destroy(key)
+    finally:
+        e.close()
+
+
+def test_salsa20_bulk_1gib_sampled(ms):
+    """The bulk workload under Salsa20/20 (262144 pages, nonce = page
+    index): the first, last and a seeded sample of pages against the
+    oracle, and the round trip in full."""
+    _note("salsa20 bulk 1GiB")
+    import torch
+    b = workloads.bulk(seed=2)
+    n = b.data.shape[0]
+    e = ms.Engine(0, cipher=ms.MS_CIPHER_SALSA)
+    try:
+        key = e.key_load(b.key)
+        src = _dev(b.data)
+        dst = torch.empty_like(src)
+        nonce = ms.linear_nonce(b.nonce_base, b.nonce_stride, b.nonce_tag)
+        e.encrypt_pages(key, src, dst, nonce)
+        idx = sorted(set([0, 1, n - 1] + np.random.default_rng(2).integers(
+            0, n, 64).tolist()))
+        got = _host(dst).reshape(n, 4096)[idx]
+        nn = oracle.nonces_linear(n, b.nonce_base, b.nonce_stride,
+                                  b.nonce_tag)[idx]
+        want = oracle.cipher_pages(b.key, nn, b.data[idx], cipher="salsa")
+        assert np.array_equal(got, want)
+        e.decrypt_pages(key, dst, dst, nonce)
+        assert torch.equal(dst, src)
+        e.key_destroy(key)
+        del src, dst
+    finally:
+        e.close()
+
+
+def test_salsa20_context_refuses_resident_engine(ms):
+    e = ms.Engine(0, cipher=ms.MS_CIPHER_SALSA)
+    try:
+        st, h = ms.ms_resident_start(e.ctx, None, bytes(32))
+        assert st == ms.MS_ENOTSUP and not h
+    finally:
+        e.close()
+
+
+def test_plain_launch_info_names_the_launch(ms, eng):
+    """ms_plain_launch_info describes what a call launches: the kernel's
+    template arguments, one launch per 2^24 pages, a grid of the resident
+    waves (or one wave per page below that)."""
+    st, i = ms.ms_plain_launch_info(eng.ctx, 262144, ms.MS_NONCE_LINEAR)
+    assert st == 0
+    assert i.kernel.decode() == "plain_pages_kernel<0u, 20, 2, 1u>"
+    assert i.launches == 1 and i.block_threads == 256
+    cus = ms.ms_device_cu_count(eng.ctx)
+    assert i.grid_blocks == cus * i.waves_per_cu // 4
+    st, i = ms.ms_plain_launch_info(eng.ctx, (1 << 24) + 3, ms.MS_NONCE_ARRAY)
+    assert st == 0 and i.launches == 2
+    assert i.kernel.decode() == "plain_pages_kernel<0u, 20, 2, 0u>"
+    st, i = ms.ms_plain_launch_info(eng.ctx, 10, ms.MS_NONCE_LINEAR)
+    assert st == 0 and i.grid_blocks == 3
+    e = ms.Engine(0, cipher=ms.MS_CIPHER_SALSA, rounds=12)
+    try:
+        st, i = ms.ms_plain_launch_info(e.ctx, 5, ms.MS_NONCE_LINEAR)
+        assert i.kernel.decode() == "plain_pages_kernel<1u, 12, 2, 1u>"
+    finally:
+        e.close()
+    assert ms.ms_plain_launch_info(eng.ctx, 0, 1)[0] == ms.MS_EINVAL

@@ -1,8 +1,10 @@
 """GPU tests of the serving path: continuous batching through ms_submit /
 ms_poll, admission by device memory, back-pressure, cancellation, prefetch
-hints, and the native load generator.  Every output checked here is compared
-with the CPU oracle on that request alone (tolerance 0: the cipher is integer
-arithmetic)."""
+hints, and the native load generator, on both serving stages (fused
+launches formed by the scheduler, and the ring: a resident kernel on the
+context's own HSA queue that reads one descriptor per page from mapped
+memory).  Every output checked here is compared with the CPU oracle on that
+request alone (tolerance 0: the cipher is integer arithmetic)."""
 import os
 import sys
 import threading
@@ -28,6 +30,10 @@ def _note(msg):
 def ms():
     from paper_2004_09252_amd import memshield
     return memshield
+
+
+# serving stages: MS_SERVE_STAGE_LAUNCH (1) and MS_SERVE_STAGE_RING (2)
+STAGES = pytest.mark.parametrize("stage", [1, 2], ids=["launch", "ring"])
 
 
 def _oracle_req(key, va, pid, data):
@@ -81,15 +87,16 @@ class _Reqs:
         return t[s:s + int(self.pages[i]) * 4096].cpu().numpy()
 
 
-def test_alone_equals_mix_equals_oracle(ms):
+@STAGES
+def test_alone_equals_mix_equals_oracle(ms, stage):
     """Each request's result is the same submitted alone (one at a time,
     waiting for each) and in the mix (submitted concurrently from 8
     threads, 12 requests per call, batched by the scheduler).  A call's
     requests are queued together, so every launch serves at least one
     call's worth: the batching does not depend on how fast the device
     finishes a request before the next call arrives."""
-    _note("alone vs mix, 96 requests")
-    eng = ms.Engine(0)
+    _note("alone vs mix, 96 requests, stage %d" % stage)
+    eng = ms.Engine(0, serve_stage=stage)
     try:
         r = _Reqs(ms, eng, seed=41, n=96)
         for i in range(96):
@@ -113,9 +120,10 @@ def test_alone_equals_mix_equals_oracle(ms):
         st, done = eng.poll(tickets, timeout_s=60)
         assert st == 0 and all(d == 1 for d in done)
         after = eng.stats()
-        # the mix was served by fused launches of at least one call each
-        assert after.batches - before.batches <= 8
-        assert after.max_batch_requests > 1
+        if stage == ms.MS_SERVE_STAGE_LAUNCH:
+            # the mix was served by fused launches of at least one call each
+            assert after.batches - before.batches <= 8
+            assert after.max_batch_requests > 1
         for i in range(96):
             a = r.slice(r.dst_a, i)
             b = r.slice(r.dst_b, i)
@@ -146,10 +154,11 @@ def test_batches_overlap_on_device(ms):
     assert out["overlapped"] >= 1, out
 
 
-def test_admission_cap_bounds_inflight_bytes(ms):
-    _note("admission cap")
+@STAGES
+def test_admission_cap_bounds_inflight_bytes(ms, stage):
+    _note("admission cap, stage %d" % stage)
     cap = 64 * 4096
-    eng = ms.Engine(0, admission_cap_bytes=cap)
+    eng = ms.Engine(0, admission_cap_bytes=cap, serve_stage=stage)
     try:
         r = _Reqs(ms, eng, seed=43, n=60, max_pages=32)
         tickets = eng.submit([r.req(i, r.dst_a) for i in range(60)])
@@ -170,9 +179,10 @@ def test_admission_cap_bounds_inflight_bytes(ms):
         eng.close()
 
 
-def test_queue_full_is_eagain_and_all_or_nothing(ms):
-    _note("eagain")
-    eng = ms.Engine(0, queue_depth=4)
+@STAGES
+def test_queue_full_is_eagain_and_all_or_nothing(ms, stage):
+    _note("eagain, stage %d" % stage)
+    eng = ms.Engine(0, queue_depth=4, serve_stage=stage)
     try:
         r = _Reqs(ms, eng, seed=44, n=5, max_pages=4)
         st, _ = ms.ms_submit(eng.ctx, [r.req(i, r.dst_a) for i in range(5)])
@@ -185,11 +195,12 @@ def test_queue_full_is_eagain_and_all_or_nothing(ms):
         eng.close()
 
 
-def test_cancel_client_keeps_others_exact(ms):
+@STAGES
+def test_cancel_client_keeps_others_exact(ms, stage):
     """Cancelling a client drops its queued requests (their tickets read
     MS_ECANCELED); every other client's results stay bit-exact."""
-    _note("cancel client")
-    eng = ms.Engine(0, admission_cap_bytes=16 * 4096)
+    _note("cancel client, stage %d" % stage)
+    eng = ms.Engine(0, admission_cap_bytes=16 * 4096, serve_stage=stage)
     try:
         r = _Reqs(ms, eng, seed=45, n=120, max_pages=16, n_clients=3)
         tickets = eng.submit([r.req(i, r.dst_a) for i in range(120)])
@@ -210,9 +221,10 @@ def test_cancel_client_keeps_others_exact(ms):
         eng.close()
 
 
-def test_key_destroy_while_queued_is_ebusy(ms):
-    _note("destroy busy")
-    eng = ms.Engine(0, admission_cap_bytes=4 * 4096)
+@STAGES
+def test_key_destroy_while_queued_is_ebusy(ms, stage):
+    _note("destroy busy, stage %d" % stage)
+    eng = ms.Engine(0, admission_cap_bytes=4 * 4096, serve_stage=stage)
     try:
         r = _Reqs(ms, eng, seed=46, n=400, max_pages=4, n_clients=1)
         tickets = eng.submit([r.req(i, r.dst_a) for i in range(400)])
@@ -226,9 +238,10 @@ def test_key_destroy_while_queued_is_ebusy(ms):
         eng.close()
 
 
-def test_prefetch_hints_run_or_drop(ms):
-    _note("prefetch hints")
-    eng = ms.Engine(0, prefetch_depth=4)
+@STAGES
+def test_prefetch_hints_run_or_drop(ms, stage):
+    _note("prefetch hints, stage %d" % stage)
+    eng = ms.Engine(0, prefetch_depth=4, serve_stage=stage)
     try:
         r = _Reqs(ms, eng, seed=47, n=8, max_pages=8)
         dropped = eng.prefetch_hint([r.req(i, r.dst_a) for i in range(5)])
@@ -249,14 +262,15 @@ def test_prefetch_hints_run_or_drop(ms):
         eng.close()
 
 
-def test_sporadic_request_after_idle_is_reaped_promptly(ms):
+@STAGES
+def test_sporadic_request_after_idle_is_reaped_promptly(ms, stage):
     """A request arriving after the scheduler has gone to sleep (spin window
     shortened to 100 us) is launched by the submitting thread; the scheduler
     must wake for it and complete the ticket promptly, not at the end of its
     2 ms sleep.  Median of 7 such requests, each checked against the
     oracle."""
-    _note("sporadic request after idle")
-    eng = ms.Engine(0, serve_spin_us=100)
+    _note("sporadic request after idle, stage %d" % stage)
+    eng = ms.Engine(0, serve_spin_us=100, serve_stage=stage)
     try:
         r = _Reqs(ms, eng, seed=43, n=7, max_pages=4)
         lat = []
@@ -275,19 +289,19 @@ def test_sporadic_request_after_idle_is_reaped_promptly(ms):
         eng.close()
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
-def test_loadgen_poisson_sample_exact(ms, mode):
+@pytest.mark.parametrize("mode,stage", [(0, 1), (0, 2), (1, 0), (2, 0)])
+def test_loadgen_poisson_sample_exact(ms, mode, stage):
     """Poisson arrivals (20k req/s, 0.5 s) through the native load
-    generator (continuous batching, a launch per request, the resident-key
-    ring with all 64 client keys); every 25th request's output is checked
-    against the oracle."""
-    _note("loadgen mode=%d" % mode)
+    generator (continuous batching on either serving stage, a launch per
+    request, the resident-key ring with all 64 client keys); every 25th
+    request's output is checked against the oracle."""
+    _note("loadgen mode=%d stage=%d" % (mode, stage))
     import torch
     from paper_2004_09252_amd import serving
     pool_pages = 16384
     w = workloads.serving(seed=4, rate_hz=20000, duration_s=0.5,
                           pool_pages=pool_pages)
-    eng = ms.Engine(0)
+    eng = ms.Engine(0, serve_stage=stage)
     try:
         keys = [eng.key_load(k) for k in w.keys]
         src = torch.empty(pool_pages * 4096, dtype=torch.uint8, device="cuda")
@@ -296,7 +310,9 @@ def test_loadgen_poisson_sample_exact(ms, mode):
         dst = torch.zeros(lay.dst_pages * 4096, dtype=torch.uint8,
                           device="cuda")
         res, lat = serving.run(eng, lay, keys, src, dst, mode)
-        assert res.completed == lay.trace.n and res.failed == 0
+        assert res.completed == lay.trace.n
+        assert res.failed == 0, "%d failed, first: request %d state %d" % (
+            res.failed, res.first_failed - 1, res.first_failed_state)
         assert res.p50_us > 0 and res.p99_us >= res.p50_us
         assert np.all(lat > 0)
         a = lay.arrays
@@ -345,15 +361,100 @@ def test_large_submitted_request_every_tiling(ms, tiling):
         eng.close()
 
 
-def test_engine_holds_tensors_of_requests_in_flight(ms):
+def test_ring_requests_overlap_a_running_launch(ms):
+    """On the ring stage, small requests submitted while a large request
+    (above the ring's page limit, so a fused launch, here on a narrow grid)
+    runs are served by the resident kernel on its own HSA queue and finish
+    before it: overlap on the device does not depend on the process's
+    streams.  Their outputs equal the oracle."""
+    _note("ring overlap with a running launch")
+    import torch
+    eng = ms.Engine(0, serve_stage=ms.MS_SERVE_STAGE_RING)
+    try:
+        rng = np.random.default_rng(48)
+        kb = [rng.bytes(32) for _ in range(2)]
+        keys = [eng.key_load(k) for k in kb]
+        small = workloads.random_pages(rng, 12)
+        src = torch.from_numpy(small.reshape(-1).copy()).to("cuda")
+        dst = torch.zeros_like(src)
+        big_pages = 65536
+        big = torch.zeros(big_pages * 4096, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+
+        def small_req(i):
+            return ms.request(keys[1], src, dst, 2,
+                              ms.linear_nonce(4096 * i, 1, 7),
+                              src_offset_pages=2 * i, dst_offset_pages=2 * i)
+
+        t = eng.submit([small_req(0)])   # the ring is up
+        assert eng.poll(t, timeout_s=30)[0] == 0
+        assert ms.ms_set_tuning(eng.ctx, ms.ms_tuning(64, 1, 2, 0, 0.0)) == 0
+        tb = eng.submit([ms.request(keys[0], big, big, big_pages,
+                                    ms.linear_nonce(0, 1, 0))])
+        overlapped = 0
+        for i in range(6):
+            ts = eng.submit([small_req(i)])
+            st, d = eng.poll(ts, timeout_s=30)
+            assert st == 0 and d == [1]
+            overlapped += eng.poll(tb, timeout_s=0)[1] == [0]
+        assert eng.poll(tb, timeout_s=60)[0] == 0
+        assert overlapped >= 3, overlapped
+        got = dst.cpu().numpy().reshape(12, 4096)
+        for i in range(6):
+            want = oracle.cipher_pages(kb[1], oracle.nonces_linear(
+                2, 4096 * i, 1, 7), small[2 * i:2 * i + 2])
+            assert np.array_equal(got[2 * i:2 * i + 2], want), i
+    finally:
+        ms.ms_set_tuning(eng.ctx, None)
+        eng.close()
+
+
+def test_ring_stage_refused_for_salsa20(ms):
+    st, ctx = ms.ms_init(0, _cfg(ms, cipher=ms.MS_CIPHER_SALSA,
+                                 serve_stage=ms.MS_SERVE_STAGE_RING))
+    assert st == ms.MS_ENOTSUP and ctx.value is None
+
+
+def _cfg(ms, **kw):
+    c = ms.ms_config_default()
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_salsa20_context_serves_through_launches(ms):
+    """A Salsa20 context's submissions (default stage) run on the fused
+    launches and equal the Salsa20 oracle."""
+    _note("salsa20 served")
+    eng = ms.Engine(0, cipher=ms.MS_CIPHER_SALSA)
+    try:
+        r = _Reqs(ms, eng, seed=49, n=20, max_pages=16)
+        t = eng.submit([r.req(i, r.dst_a) for i in range(20)])
+        st, done = eng.poll(t, timeout_s=30)
+        assert st == 0 and all(d == 1 for d in done)
+        for i in range(20):
+            s0 = int(r.off[i]) * 4096
+            e0 = s0 + int(r.pages[i]) * 4096
+            n = int(r.pages[i])
+            want = oracle.cipher_pages(
+                r.kbytes[r.client[i]],
+                oracle.nonces_linear(n, int(r.va[i]), 4096, int(r.pid[i])),
+                r.host[s0:e0].reshape(n, 4096), cipher="salsa").reshape(-1)
+            assert np.array_equal(r.slice(r.dst_a, i), want), i
+    finally:
+        eng.close()
+
+
+@STAGES
+def test_engine_holds_tensors_of_requests_in_flight(ms, stage):
     """A request's tensors stay alive while it is in flight even when the
     caller drops them, and are released once poll reports it finished."""
-    _note("tensors held while in flight")
+    _note("tensors held while in flight, stage %d" % stage)
     import gc
     import weakref
 
     import torch
-    eng = ms.Engine(0)
+    eng = ms.Engine(0, serve_stage=stage)
     try:
         key = eng.key_generate()
         src = torch.randint(0, 256, (256 * 4096,), dtype=torch.uint8,

@@ -35,6 +35,10 @@ COMMON = [os.path.join(CSRC, "engine.cpp"),
           os.path.join(MOCK, "mock_hip.cpp"),
           os.path.join(MOCK, "mock_kernels.cpp")]
 SCHED_SOURCES = COMMON + [os.path.join(MOCK, "sched_stress.cpp")]
+RING_SOURCES = COMMON + [os.path.join(CSRC, "host_pages.cpp"),
+                         os.path.join(CSRC, "resident.cpp"),
+                         os.path.join(MOCK, "mock_hsa.cpp"),
+                         os.path.join(MOCK, "sched_stress.cpp")]
 KEY_RACE_SOURCES = COMMON + [os.path.join(CSRC, "host_pages.cpp"),
                              os.path.join(MOCK, "key_race.cpp")]
 RESIDENT_SOURCES = COMMON + [os.path.join(CSRC, "host_pages.cpp"),
@@ -53,10 +57,11 @@ def _tsan_available(tmp_path):
     return r.returncode == 0
 
 
-def _build(tmp_path, sources, name):
+def _build(tmp_path, sources, name, defines=()):
     cxx = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=thread",
            "-include", os.path.join(MOCK, "tsan_prelude.h"),
-           "-I", MOCK, "-I", INCLUDE, "-I", CSRC]
+           "-I", MOCK, "-I", INCLUDE, "-I", CSRC] + \
+        ["-D" + d for d in defines]
     objs = [str(tmp_path / (os.path.basename(s) + ".o")) for s in sources]
     jobs = [cxx + ["-c", s, "-o", o] for s, o in zip(sources, objs)]
     jobs.append(["gcc", "-std=c99", "-O2", "-g", "-fsanitize=thread", "-c",
@@ -75,8 +80,9 @@ def _build(tmp_path, sources, name):
     return exe
 
 
-def _run_clean(exe):
-    env = dict(os.environ, TSAN_OPTIONS="second_deadlock_stack=1")
+def _run_clean(exe, **extra_env):
+    env = dict(os.environ, TSAN_OPTIONS="second_deadlock_stack=1",
+               **extra_env)
     r = subprocess.run([str(exe)], capture_output=True, text=True,
                        timeout=600, env=env)
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
@@ -89,6 +95,19 @@ def test_serving_host_logic_under_thread_sanitizer(tmp_path):
     if not _tsan_available(tmp_path):
         pytest.skip("g++ with ThreadSanitizer not available")
     _run_clean(_build(tmp_path, SCHED_SOURCES, "sched_stress"))
+
+
+def test_ring_serving_stage_host_logic_under_thread_sanitizer(tmp_path):
+    """The same serving driver with the ring stage (ms_submit publishing
+    one descriptor per page into the resident kernel's ring, which reads
+    each descriptor's key from the context's key table): alone == mix ==
+    oracle, with hints and cancellation beside it, on a mock device of 8
+    compute units (31 ring workers, each a host thread)."""
+    if not _tsan_available(tmp_path):
+        pytest.skip("g++ with ThreadSanitizer not available")
+    exe = _build(tmp_path, RING_SOURCES, "ring_stress",
+                 defines=("RING_STAGE",))
+    _run_clean(exe, MOCK_HIP_CUS="8")
 
 
 def test_resident_engine_host_logic_under_thread_sanitizer(tmp_path):
