@@ -179,7 +179,7 @@ struct ms_ctx {
   std::atomic<bool> stop{false};
   std::thread scheduler;
 
-  // serve_slots, serve_free, inflight and inflight_bytes belong to whoever
+  // serve_slots, serve_free and inflight belong to whoever
   // holds sched_mu: the scheduler thread, or a submitting thread that finds
   // the lock free and launches its own batch at once
   std::mutex sched_mu;
@@ -187,7 +187,9 @@ struct ms_ctx {
   std::vector<hipStream_t> serve_streams;
   std::vector<int> serve_free;
   std::deque<InflightBatch> inflight;
-  uint64_t inflight_bytes = 0;  // under sched_mu (mirrored in stats)
+  // page bytes admitted on either stage and not yet reaped (the admission
+  // cap applies to it; reserve_admission takes from it atomically)
+  std::atomic<uint64_t> inflight_bytes{0};
 
   // ring serving stage (serve_stage): a resident kernel on its own HSA
   // queue reads each request's pages from a descriptor ring in mapped
@@ -197,8 +199,11 @@ struct ms_ctx {
   bool ring_mode = false;
   std::atomic<ms_resident*> ring{nullptr};
   bool ring_failed = false;                 // (sched_mu)
-  std::vector<RingReq> ring_inflight;       // (sched_mu)
-  uint64_t ring_desc = 0;                   // positions held (sched_mu)
+  std::mutex ring_mu;                       // ring_inflight
+  std::vector<RingReq> ring_inflight;       // published, not yet reaped
+  std::vector<RingReq> ring_scan;           // the reaper's (sched_mu)
+  std::atomic<uint64_t> ring_desc{0};       // ring positions held
+  std::atomic<uint64_t> ring_reqs{0};       // requests published, not reaped
   uint32_t ring_depth = 1u << 16;
   uint32_t ring_workers = 0;
 
@@ -210,7 +215,7 @@ struct ms_ctx {
   // ---- stats ----
   std::atomic<uint64_t> st_submitted{0}, st_completed{0}, st_eagain{0},
       st_batches{0}, st_pages{0}, st_pf_issued{0}, st_pf_dropped{0},
-      st_cancelled{0}, st_inflight_bytes{0}, st_max_inflight{0},
+      st_cancelled{0}, st_max_inflight{0},
       st_max_batch{0}, st_max_inflight_batches{0};
 };
 
@@ -574,9 +579,32 @@ void finish_batch(ms_ctx* c, InflightBatch& b, int32_t state) {
   }
   c->outstanding.fetch_sub(b.tickets.size());
   c->st_completed.fetch_add(b.tickets.size());
-  c->inflight_bytes -= b.bytes;
-  c->st_inflight_bytes.store(c->inflight_bytes);
+  c->inflight_bytes.fetch_sub(b.bytes);
   c->serve_free.push_back(b.slot);
+}
+
+// Take `bytes` of the admission cap and `positions` ring positions, both or
+// neither.  Lock-free: submitting threads and the scheduler reserve at once.
+bool reserve_admission(ms_ctx* c, uint64_t bytes, uint64_t positions) {
+  const uint64_t cap = c->cfg.admission_cap_bytes;
+  uint64_t b = c->inflight_bytes.load(std::memory_order_relaxed);
+  do {
+    if (b + bytes > cap) return false;
+  } while (!c->inflight_bytes.compare_exchange_weak(b, b + bytes));
+  if (positions) {
+    uint64_t d = c->ring_desc.load(std::memory_order_relaxed);
+    do {
+      if (d + positions > c->ring_depth) {
+        c->inflight_bytes.fetch_sub(bytes);
+        return false;
+      }
+    } while (!c->ring_desc.compare_exchange_weak(d, d + positions));
+  }
+  const uint64_t now = b + bytes;
+  uint64_t hi = c->st_max_inflight.load(std::memory_order_relaxed);
+  while (now > hi && !c->st_max_inflight.compare_exchange_weak(hi, now)) {
+  }
+  return true;
 }
 
 void complete_ticket_now(ms_ctx* c, uint32_t t, int32_t state,
@@ -628,7 +656,7 @@ bool launch_one(ms_ctx* c) {
     const size_t maxn = c->cfg.max_batch_requests;
     while (!c->demand_q.empty() && take.size() < maxn) {
       const uint64_t b = c->demand_q.front().req.n_pages * MS_PAGE_SIZE;
-      if (c->inflight_bytes + bytes + b > cap) break;
+      if (!reserve_admission(c, b, 0)) break;
       bytes += b;
       take.push_back(c->demand_q.front());
       c->demand_q.pop_front();
@@ -637,13 +665,14 @@ bool launch_one(ms_ctx* c) {
     if (c->demand_q.empty()) {
       while (!c->prefetch_q.empty() && take.size() < maxn) {
         const uint64_t b = c->prefetch_q.front().req.n_pages * MS_PAGE_SIZE;
-        if (c->inflight_bytes + bytes + b > cap) break;
+        if (!reserve_admission(c, b, 0)) break;
         bytes += b;
         take.push_back(c->prefetch_q.front());
         c->prefetch_q.pop_front();
       }
     }
   }
+  (void)cap;
   if (take.empty()) return false;
   const int slot = c->serve_free.back();
   c->serve_free.pop_back();
@@ -666,10 +695,6 @@ bool launch_one(ms_ctx* c) {
   }
   uint64_t total = 0;
   const size_t copy = fill_slot(s, rp.data(), ks.data(), take.size(), &total);
-  c->inflight_bytes += bytes;
-  c->st_inflight_bytes.store(c->inflight_bytes);
-  if (c->inflight_bytes > c->st_max_inflight.load())
-    c->st_max_inflight.store(c->inflight_bytes);
   if (take.size() > c->st_max_batch.load()) c->st_max_batch.store(take.size());
   c->st_batches.fetch_add(1);
   c->st_pages.fetch_add(total);
@@ -748,30 +773,78 @@ void finish_ring_req(ms_ctx* c, const RingReq& q, int32_t state) {
   }
   c->outstanding.fetch_sub(1);
   c->st_completed.fetch_add(1);
-  c->inflight_bytes -= q.bytes;
-  c->st_inflight_bytes.store(c->inflight_bytes);
-  c->ring_desc -= q.desc;
+  c->inflight_bytes.fetch_sub(q.bytes);
+  c->ring_desc.fetch_sub(q.desc);
+  c->ring_reqs.fetch_sub(1);
 }
 
-// Mark finished ring requests complete; true when any was.
+// Publish one queued request whose admission bytes and ring positions are
+// already reserved; on failure its ticket completes with the error.  Any
+// thread may call it (the ring has its own lock; the list of published
+// requests has ring_mu).
+void publish_reserved(ms_ctx* c, ms_resident* r, const Pending& p) {
+  const uint32_t ks = (uint32_t)(p.req.key & 0xffffffffu) - 1;
+  const uint64_t bytes = p.req.n_pages * MS_PAGE_SIZE;
+  ms_ticket rt = 0;
+  const ms_status st = ms_internal_ring_publish(
+      r, ks, p.req.src, p.req.dst, p.req.n_pages, p.req.nonce, &rt);
+  if (st) {
+    // (MS_EAGAIN cannot happen: positions are counted until reaped)
+    c->sticky_error.store(MS_EDEVICE);
+    c->inflight_bytes.fetch_sub(bytes);
+    c->ring_desc.fetch_sub(p.req.n_pages);
+    complete_ticket_now(c, p.ticket_slot, st == MS_EAGAIN ? MS_EDEVICE : st,
+                        ks);
+    return;
+  }
+  RingReq q;
+  q.ticket_slot = p.ticket_slot;
+  q.key_slot = ks;
+  q.ring_ticket = rt;
+  q.bytes = bytes;
+  q.desc = p.req.n_pages;
+  c->ring_reqs.fetch_add(1);
+  {
+    std::lock_guard<std::mutex> lk(c->ring_mu);
+    c->ring_inflight.push_back(q);
+  }
+  c->tickets[p.ticket_slot].ring.store(rt, std::memory_order_release);
+  c->st_pages.fetch_add(p.req.n_pages);
+  if (p.prefetch) c->st_pf_issued.fetch_add(1);
+}
+
+// Mark finished ring requests complete (scheduler thread); true when any
+// was.  The list is taken out under ring_mu and scanned without it, so
+// submitting threads can keep publishing meanwhile.
 bool ring_reap(ms_ctx* c) {
-  ms_resident* r = c->ring.load(std::memory_order_relaxed);
-  if (!r || c->ring_inflight.empty()) return false;
+  ms_resident* r = c->ring.load(std::memory_order_acquire);
+  if (!r) return false;
+  std::vector<RingReq>& scan = c->ring_scan;
+  {
+    std::lock_guard<std::mutex> lk(c->ring_mu);
+    if (c->ring_inflight.empty()) return false;
+    scan.swap(c->ring_inflight);
+  }
   const bool gone = !ms_internal_ring_alive(r);
   bool any = false;
   size_t w = 0;
-  for (size_t i = 0; i < c->ring_inflight.size(); ++i) {
-    const RingReq q = c->ring_inflight[i];
+  for (size_t i = 0; i < scan.size(); ++i) {
+    const RingReq q = scan[i];
     const int d = ms_internal_ring_done(r, q.ring_ticket);
     if (!d && !gone) {
-      c->ring_inflight[w++] = q;
+      scan[w++] = q;
       continue;
     }
     if (!d) c->sticky_error.store(MS_EDEVICE);
     finish_ring_req(c, q, d ? 1 : MS_EDEVICE);
     any = true;
   }
-  c->ring_inflight.resize(w);
+  scan.resize(w);
+  if (!scan.empty()) {
+    std::lock_guard<std::mutex> lk(c->ring_mu);
+    c->ring_inflight.insert(c->ring_inflight.end(), scan.begin(), scan.end());
+  }
+  scan.clear();
   return any;
 }
 
@@ -797,67 +870,33 @@ bool ring_publish(ms_ctx* c) {
     return !gone.empty();
   }
   ms_resident* r = c->ring.load(std::memory_order_relaxed);
-  const uint64_t cap = c->cfg.admission_cap_bytes;
-  uint64_t published = 0, pages = 0, n_pf = 0;
+  uint64_t published = 0;
   for (;;) {
     Pending p;
-    bool have = false, pf = false;
+    bool have = false;
     {
       std::lock_guard<std::mutex> lk(c->q_mu);
       std::deque<Pending>* q = nullptr;
-      if (!c->ring_q.empty()) {
+      if (!c->ring_q.empty())
         q = &c->ring_q;
-      } else if (!c->ring_pf_q.empty() &&
-                 c->ring_desc < c->ring_workers / 2) {
+      else if (!c->ring_pf_q.empty() &&
+               c->ring_desc.load() < c->ring_workers / 2)
         q = &c->ring_pf_q;
-        pf = true;
-      }
-      if (q) {
-        const Pending& f = q->front();
-        const uint64_t b = f.req.n_pages * MS_PAGE_SIZE;
-        if (c->inflight_bytes + b <= cap &&
-            c->ring_desc + f.req.n_pages <= c->ring_depth) {
-          p = f;
-          q->pop_front();
-          have = true;
-        }
+      if (q && reserve_admission(c, q->front().req.n_pages * MS_PAGE_SIZE,
+                                 q->front().req.n_pages)) {
+        p = q->front();
+        q->pop_front();
+        have = true;
       }
     }
     if (!have) break;
-    const uint32_t ks = (uint32_t)(p.req.key & 0xffffffffu) - 1;
-    ms_ticket rt = 0;
-    const ms_status st = ms_internal_ring_publish(
-        r, ks, p.req.src, p.req.dst, p.req.n_pages, p.req.nonce, &rt);
-    any = true;
-    if (st) {
-      // (MS_EAGAIN cannot happen: positions are counted until reaped)
-      if (st != MS_EAGAIN) c->sticky_error.store(MS_EDEVICE);
-      complete_ticket_now(c, p.ticket_slot, st == MS_EAGAIN ? MS_EDEVICE : st,
-                          ks);
-      continue;
-    }
-    c->tickets[p.ticket_slot].ring.store(rt, std::memory_order_release);
-    RingReq q;
-    q.ticket_slot = p.ticket_slot;
-    q.key_slot = ks;
-    q.ring_ticket = rt;
-    q.bytes = p.req.n_pages * MS_PAGE_SIZE;
-    q.desc = p.req.n_pages;
-    c->ring_inflight.push_back(q);
-    c->ring_desc += q.desc;
-    c->inflight_bytes += q.bytes;
+    publish_reserved(c, r, p);
     ++published;
-    pages += p.req.n_pages;
-    n_pf += pf ? 1 : 0;
+    any = true;
   }
   if (published) {
-    c->st_inflight_bytes.store(c->inflight_bytes);
-    if (c->inflight_bytes > c->st_max_inflight.load())
-      c->st_max_inflight.store(c->inflight_bytes);
     if (published > c->st_max_batch.load()) c->st_max_batch.store(published);
     c->st_batches.fetch_add(1);
-    c->st_pages.fetch_add(pages);
-    c->st_pf_issued.fetch_add(n_pf);
   }
   return any;
 }
@@ -882,7 +921,7 @@ void scheduler_main(ms_ctx* c) {
         did = ring_publish(c) || did;
       }
       while (launch_one(c)) did = true;
-      idle_device = c->inflight.empty() && c->ring_inflight.empty();
+      idle_device = c->inflight.empty() && c->ring_reqs.load() == 0;
     }
     if (did) {
       last_work = Clock::now();
@@ -1011,6 +1050,13 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
     c->outstanding.fetch_sub(n);
     return st;
   }
+  // On the ring stage a small request that nothing waits before, and that
+  // fits the admission cap and the ring, is published by this thread at
+  // once (a reservation is two atomic updates; the ring has its own lock);
+  // the others queue for the scheduler.
+  std::vector<Pending> direct;
+  ms_resident* ring =
+      c->ring_mode ? c->ring.load(std::memory_order_acquire) : nullptr;
   {
     std::lock_guard<std::mutex> lk(c->q_mu);
     for (size_t i = 0; i < n; ++i) {
@@ -1020,11 +1066,27 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
       p.req.key = (reqs[i].key & 0xffffffff00000000ull) | (ks[i] + 1);
       p.ticket_slot = ts[i];
       p.prefetch = prefetch;
-      if (c->ring_mode && reqs[i].n_pages <= kRingMaxPages)
-        (prefetch ? c->ring_pf_q : c->ring_q).push_back(p);
-      else
+      if (c->ring_mode && reqs[i].n_pages <= kRingMaxPages) {
+        const bool first = prefetch
+                               ? c->ring_q.empty() && c->ring_pf_q.empty() &&
+                                     c->ring_desc.load() < c->ring_workers / 2
+                               : c->ring_q.empty();
+        if (ring && first &&
+            reserve_admission(c, reqs[i].n_pages * MS_PAGE_SIZE,
+                              reqs[i].n_pages))
+          direct.push_back(p);
+        else
+          (prefetch ? c->ring_pf_q : c->ring_q).push_back(p);
+      } else {
         (prefetch ? c->prefetch_q : c->demand_q).push_back(p);
+      }
     }
+  }
+  for (const Pending& p : direct) publish_reserved(c, ring, p);
+  if (!direct.empty()) {
+    c->st_batches.fetch_add(1);
+    if (direct.size() > c->st_max_batch.load())
+      c->st_max_batch.store(direct.size());
   }
   if (!prefetch) {
     // direct launch on an idle device: if no batch is in flight and the
@@ -1035,8 +1097,9 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
     // On the ring stage the submitting thread publishes its small
     // requests itself whenever the lock is free: a publication is a few
     // stores into mapped memory.
-    std::unique_lock<std::mutex> lk(c->sched_mu, std::try_to_lock);
-    if (lk.owns_lock() && (c->ring_mode || c->inflight.empty())) {
+    std::unique_lock<std::mutex> lk(c->sched_mu, std::defer_lock);
+    if (direct.size() < n && lk.try_lock() &&
+        (c->ring_mode || c->inflight.empty())) {
       int prev = c->device;
       (void)hipGetDevice(&prev);
       if (prev != c->device) (void)hipSetDevice(c->device);
@@ -1720,7 +1783,7 @@ ms_status ms_get_stats(ms_ctx* c, ms_stats* o) {
   o->prefetch_issued = c->st_pf_issued.load();
   o->prefetch_dropped = c->st_pf_dropped.load();
   o->cancelled = c->st_cancelled.load();
-  o->inflight_bytes = c->st_inflight_bytes.load();
+  o->inflight_bytes = c->inflight_bytes.load();
   o->max_inflight_bytes = c->st_max_inflight.load();
   o->max_batch_requests = c->st_max_batch.load();
   o->max_inflight_batches = c->st_max_inflight_batches.load();

@@ -140,14 +140,14 @@ __device__ __forceinline__ void cipher_run(const uint32_t (&kk)[8],
                                            uint64_t nb, uint64_t ns,
                                            uint32_t tag, uint32_t n_pages,
                                            uint4* lds, uint32_t lane) {
-  for (uint32_t p = 0; p < n_pages; ++p) {
+  // the page's 512 8-byte units: access q of lane l is unit 64*q + l
+  auto load = [&](uint64_t (&v)[8], uint32_t p) {
     const uint64_t s = src + (uint64_t)p * kPageBytes;
-    const uint64_t o = dst + (uint64_t)p * kPageBytes;
-    // the page's 512 8-byte units: access q of lane l is unit 64*q + l,
-    // issued before the keystream so the link latency overlaps the rounds
-    uint64_t v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q] = ld_page(s + 8u * (q * 64 + lane));
+  };
+  auto cipher = [&](const uint64_t (&v)[8], uint32_t p) {
+    const uint64_t o = dst + (uint64_t)p * kPageBytes;
     uint32_t n[3];
     if (ARRAY) {
       const uint32_t* na =
@@ -176,6 +176,22 @@ __device__ __forceinline__ void cipher_run(const uint32_t (&kk)[8],
       st_page(o + 8u * unit, v[q] ^ (((uint64_t)x.y << 32) | x.x));
     }
     wave_lds_order();
+  };
+  // Two page buffers: the next page's loads are in flight while the
+  // current page's keystream is computed and stored (a worker is the only
+  // wave on its SIMD, so nothing else would hide that latency).  The page
+  // count is wave-uniform, so these branches are scalar.
+  uint64_t va[8], vb[8];
+  load(va, 0);
+  for (uint32_t p = 0;; p += 2) {
+    const bool more_b = p + 1 < n_pages;
+    if (more_b) load(vb, p + 1);
+    cipher(va, p);
+    if (!more_b) break;
+    const bool more_a = p + 2 < n_pages;
+    if (more_a) load(va, p + 2);
+    cipher(vb, p + 1);
+    if (!more_a) break;
   }
 }
 
