@@ -9,10 +9,20 @@ Usage (from the repository root, on the databases a profiling run left):
         <out.txt> <cmd-fetch> <cmd-write>
     python -m paper_2004_09252_amd.profsum valu <valu.db> <out.txt> <cmd>
     python -m paper_2004_09252_amd.profsum host <csv-dir> <out.md> <cmd>
+    python -m paper_2004_09252_amd.profsum resident <trace.db> <fetch.db> \
+        <write.db> <sq.db> <pages> <out.txt> <cmd-prefix>
 
 ``trace`` writes the kernel-trace statistics (rocprofv3 --kernel-trace
 --stats): per kernel and grid size, the number of dispatches and their
 average, minimum and maximum duration.
+
+``resident`` summarises one run of the resident-key kernel on HBM pages
+(bench.py --resident-device-only): its dispatch duration, HBM bytes per page
+(FETCH_SIZE and WRITE_SIZE calibrated on the copy probe of the same run),
+vector instructions per page, and the share of wave cycles spent waiting.
+The kernel is one dispatch for the whole engine lifetime, so the counters
+include its idle polling between tickets; ``pages`` is the number of pages
+the run pushed through it.
 
 ``traffic`` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch) into HBM bytes
 per launch of the bulk plain page kernel.  Both counters are first calibrated
@@ -238,7 +248,64 @@ def host(trace_dir: str, out_path: str, cmd: str) -> None:
         f.write("\n".join(lines) + "\n")
 
 
+RESIDENT_KERNEL = "ms_resident_pages"
+
+
+def resident(trace_db: str, fetch_db: str, write_db: str, sq_db: str,
+             pages: int, out_path: str, cmd: str) -> None:
+    db = sqlite3.connect(trace_db)
+    rows = [r for r in db.execute(
+        "select name, duration, vgpr_count, sgpr_count, lds_size, grid_x, "
+        "workgroup_x from kernels") if RESIDENT_KERNEL in r[0]]
+    durs = [r[1] for r in rows]
+    f = _counter(fetch_db, "FETCH_SIZE")
+    w = _counter(write_db, "WRITE_SIZE")
+    kf, _ = _pick(f, RESIDENT_KERNEL)
+    cf, _ = _pick(f, COPY_KERNEL)
+    kw, _ = _pick(w, RESIDENT_KERNEL)
+    cw, _ = _pick(w, COPY_KERNEL)
+    fetch_b = kf * 1024.0 * COPY_BYTES / (cf * 1024.0)
+    write_b = kw * 1024.0 * COPY_BYTES / (cw * 1024.0)
+    sq = {c: _pick(_counter(sq_db, c), RESIDENT_KERNEL)[0]
+          for c in ("SQ_INSTS_VALU", "SQ_WAVES", "SQ_BUSY_CYCLES",
+                    "SQ_WAIT_ANY", "SQ_WAVE_CYCLES", "GRBM_GUI_ACTIVE")}
+    lines = [
+        "# rocprofv3 summary of the resident-key kernel on HBM pages",
+        "# trace command: " + cmd + " --kernel-trace --stats",
+        "# counter commands: the same with --pmc FETCH_SIZE, then "
+        "--pmc WRITE_SIZE, then --pmc SQ_INSTS_VALU SQ_WAVES SQ_BUSY_CYCLES "
+        "SQ_WAIT_ANY SQ_WAVE_CYCLES GRBM_GUI_ACTIVE",
+        "# one dispatch spans the engine's life, idle polling included",
+        "kernel: %s" % RESIDENT_KERNEL,
+        "dispatches_traced: %d" % len(durs),
+        "dispatch_duration_ms: %.3f" % (
+            (sum(durs) / len(durs) / 1e6) if durs else float("nan")),
+        "vgprs_sgprs_lds_bytes: %s" % (
+            "%d %d %d" % rows[0][2:5] if rows else "n/a"),
+        "workgroups_x_threads: %s" % (
+            "%d x %d" % (rows[0][5] // max(rows[0][6], 1), rows[0][6])
+            if rows else "n/a"),
+        "pages_processed: %d" % pages,
+        "hbm_fetch_bytes_per_page: %.1f" % (fetch_b / pages),
+        "hbm_write_bytes_per_page: %.1f" % (write_b / pages),
+        "algorithmic_bytes_per_page: %d" % (2 * 4096),
+        "valu_instructions_per_page: %.1f" % (sq["SQ_INSTS_VALU"] / pages),
+        "waves: %.0f" % sq["SQ_WAVES"],
+        "wave_cycles_waiting_frac: %.4f" % (sq["SQ_WAIT_ANY"] /
+                                            sq["SQ_WAVE_CYCLES"]),
+        "sq_busy_cycles: %.0f" % sq["SQ_BUSY_CYCLES"],
+        "grbm_gui_active_cycles_per_xcd: %.0f" % (sq["GRBM_GUI_ACTIVE"] /
+                                                  N_XCD),
+    ]
+    with open(out_path, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+
+
 def main(argv):
+    if len(argv) >= 9 and argv[1] == "resident":
+        resident(argv[2], argv[3], argv[4], argv[5], int(argv[6]), argv[7],
+                 " ".join(argv[8:]))
+        return 0
     if len(argv) >= 5 and argv[1] == "host":
         host(argv[2], argv[3], " ".join(argv[4:]))
         return 0
