@@ -23,6 +23,10 @@
  *     observes completion words in host memory, and the engine is stopped
  *     at the end.  This is the paper's own serving design (a kernel that
  *     never ends, fed through a ring in mapped memory) on device pages.
+ * Before the first arrival each mode runs one warm-up request (the first
+ * page of request 0) through its own path and waits for it, so that
+ * one-time costs (the serving stage's start, a first launch) stay out of
+ * the measured latencies.
  * The paper's server handles many clients' page requests concurrently
  * through per-worker multiple-producer queues (section 4.4); this harness
  * drives the engine's equivalent with synthetic traffic.

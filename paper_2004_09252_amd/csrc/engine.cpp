@@ -106,13 +106,22 @@ struct TicketSlot {
   std::atomic<uint64_t> ring{0};
 };
 
-// A request published on the ring serving stage, not yet reaped.
-struct RingReq {
+// What the reaper needs of a request published on the ring serving stage,
+// kept at its first ring position modulo the ring depth.  The publisher
+// stores `seq` (first position + 1) last, with release order, so a reaper
+// that reads a matching `seq` sees the other fields.
+struct RingMeta {
+  std::atomic<uint64_t> seq{0};
+  uint32_t ticket_slot = 0;
+  uint32_t key_slot = 0;
+  uint64_t n_pages = 0;
+};
+
+// A reaped ring request on its way to completion.
+struct RingDone {
   uint32_t ticket_slot;
   uint32_t key_slot;
-  ms_ticket ring_ticket;
-  uint64_t bytes;
-  uint64_t desc;  // ring positions it holds
+  int32_t state;
 };
 
 struct InflightBatch {
@@ -176,6 +185,9 @@ struct ms_ctx {
   // ring serving stage: requests of at most kRingMaxPages pages
   std::deque<Pending> ring_q;
   std::deque<Pending> ring_pf_q;
+  // their sizes, written under q_mu and read without it, so that a
+  // submission or a scheduler pass finds empty queues without the lock
+  std::atomic<uint64_t> ring_q_n{0}, ring_pf_n{0};
   std::atomic<bool> stop{false};
   std::thread scheduler;
 
@@ -199,9 +211,15 @@ struct ms_ctx {
   bool ring_mode = false;
   std::atomic<ms_resident*> ring{nullptr};
   bool ring_failed = false;                 // (sched_mu)
-  std::mutex ring_mu;                       // ring_inflight
-  std::vector<RingReq> ring_inflight;       // published, not yet reaped
-  std::vector<RingReq> ring_scan;           // the reaper's (sched_mu)
+  // Requests are reaped in ring order: ring_reap_pos is the first position
+  // of the oldest request not yet reaped, ring_done_pos the end of the
+  // ring's completed prefix (every position below it is done; ms_poll
+  // reads it too).  Both move only forward, on the thread that holds
+  // sched_mu.
+  std::unique_ptr<RingMeta[]> ring_meta;    // ring_depth entries
+  uint64_t ring_reap_pos = 0;               // (sched_mu)
+  std::atomic<uint64_t> ring_done_pos{0};
+  std::vector<RingDone> ring_batch;         // the reaper's (sched_mu)
   std::atomic<uint64_t> ring_desc{0};       // ring positions held
   std::atomic<uint64_t> ring_reqs{0};       // requests published, not reaped
   uint32_t ring_depth = 1u << 16;
@@ -763,25 +781,10 @@ ms_status ensure_ring(ms_ctx* c) {
   return MS_OK;
 }
 
-void finish_ring_req(ms_ctx* c, const RingReq& q, int32_t state) {
-  c->key_refs[q.key_slot].fetch_sub(1);
-  {
-    std::lock_guard<std::mutex> lk(c->ticket_mu);
-    c->tickets[q.ticket_slot].state.store(state, std::memory_order_release);
-    c->tickets[q.ticket_slot].ring.store(0, std::memory_order_relaxed);
-    c->ticket_free.push_back(q.ticket_slot);
-  }
-  c->outstanding.fetch_sub(1);
-  c->st_completed.fetch_add(1);
-  c->inflight_bytes.fetch_sub(q.bytes);
-  c->ring_desc.fetch_sub(q.desc);
-  c->ring_reqs.fetch_sub(1);
-}
-
 // Publish one queued request whose admission bytes and ring positions are
 // already reserved; on failure its ticket completes with the error.  Any
-// thread may call it (the ring has its own lock; the list of published
-// requests has ring_mu).
+// thread may call it (the ring has its own lock; the reaper finds the
+// request through its ring position).
 void publish_reserved(ms_ctx* c, ms_resident* r, const Pending& p) {
   const uint32_t ks = (uint32_t)(p.req.key & 0xffffffffu) - 1;
   const uint64_t bytes = p.req.n_pages * MS_PAGE_SIZE;
@@ -797,55 +800,77 @@ void publish_reserved(ms_ctx* c, ms_resident* r, const Pending& p) {
                         ks);
     return;
   }
-  RingReq q;
-  q.ticket_slot = p.ticket_slot;
-  q.key_slot = ks;
-  q.ring_ticket = rt;
-  q.bytes = bytes;
-  q.desc = p.req.n_pages;
+  uint64_t first = 0, count = 0;
+  ms_internal_ring_span(rt, &first, &count);
   c->ring_reqs.fetch_add(1);
-  {
-    std::lock_guard<std::mutex> lk(c->ring_mu);
-    c->ring_inflight.push_back(q);
-  }
   c->tickets[p.ticket_slot].ring.store(rt, std::memory_order_release);
+  RingMeta& m = c->ring_meta[first & (c->ring_depth - 1)];
+  m.ticket_slot = p.ticket_slot;
+  m.key_slot = ks;
+  m.n_pages = count;
+  m.seq.store(first + 1, std::memory_order_release);
   c->st_pages.fetch_add(p.req.n_pages);
   if (p.prefetch) c->st_pf_issued.fetch_add(1);
 }
 
-// Mark finished ring requests complete (scheduler thread); true when any
-// was.  The list is taken out under ring_mu and scanned without it, so
-// submitting threads can keep publishing meanwhile.
+// Complete finished ring requests (caller holds sched_mu); true when any
+// was.  Requests are taken in ring order from the oldest: a request is
+// finished once the ring's completed prefix covers its positions, and the
+// walk stops at the first that is not (or whose publisher has not yet
+// recorded it), so a pass costs one read per newly completed position plus
+// one per request it finishes, not one per request in flight.  What the
+// finished requests hold (tickets, admission bytes, ring positions) is
+// released together, under one lock.
 bool ring_reap(ms_ctx* c) {
   ms_resident* r = c->ring.load(std::memory_order_acquire);
-  if (!r) return false;
-  std::vector<RingReq>& scan = c->ring_scan;
-  {
-    std::lock_guard<std::mutex> lk(c->ring_mu);
-    if (c->ring_inflight.empty()) return false;
-    scan.swap(c->ring_inflight);
-  }
+  if (!r || c->ring_reqs.load(std::memory_order_acquire) == 0) return false;
+  const uint64_t mask = c->ring_depth - 1;
+  const uint64_t published = ms_internal_ring_published(r);
   const bool gone = !ms_internal_ring_alive(r);
-  bool any = false;
-  size_t w = 0;
-  for (size_t i = 0; i < scan.size(); ++i) {
-    const RingReq q = scan[i];
-    const int d = ms_internal_ring_done(r, q.ring_ticket);
-    if (!d && !gone) {
-      scan[w++] = q;
-      continue;
+  const uint64_t done = ms_internal_ring_advance(
+      r, c->ring_done_pos.load(std::memory_order_relaxed), published);
+  c->ring_done_pos.store(done, std::memory_order_release);
+  std::vector<RingDone>& batch = c->ring_batch;
+  batch.clear();
+  uint64_t pos = c->ring_reap_pos, pages = 0;
+  while (pos < published) {
+    const RingMeta& m = c->ring_meta[pos & mask];
+    if (m.seq.load(std::memory_order_acquire) != pos + 1) break;
+    int32_t state = 1;
+    if (pos + m.n_pages > done) {
+      if (!gone) break;
+      // the kernel has ended: what it has not completed never will (its
+      // positions may still have completed out of order)
+      const uint64_t end = pos + m.n_pages;
+      bool all = true;
+      for (uint64_t q = pos; q < end && all; ++q)
+        all = ms_internal_ring_advance(r, q, q + 1) == q + 1;
+      state = all ? 1 : MS_EDEVICE;
     }
-    if (!d) c->sticky_error.store(MS_EDEVICE);
-    finish_ring_req(c, q, d ? 1 : MS_EDEVICE);
-    any = true;
+    batch.push_back({m.ticket_slot, m.key_slot, state});
+    pages += m.n_pages;
+    pos += m.n_pages;
   }
-  scan.resize(w);
-  if (!scan.empty()) {
-    std::lock_guard<std::mutex> lk(c->ring_mu);
-    c->ring_inflight.insert(c->ring_inflight.end(), scan.begin(), scan.end());
+  if (batch.empty()) return false;
+  for (const RingDone& d : batch) c->key_refs[d.key_slot].fetch_sub(1);
+  {
+    std::lock_guard<std::mutex> lk(c->ticket_mu);
+    for (const RingDone& d : batch) {
+      TicketSlot& t = c->tickets[d.ticket_slot];
+      t.state.store(d.state, std::memory_order_release);
+      t.ring.store(0, std::memory_order_relaxed);
+      c->ticket_free.push_back(d.ticket_slot);
+      if (d.state != 1) c->sticky_error.store(MS_EDEVICE);
+    }
   }
-  scan.clear();
-  return any;
+  const uint64_t n = batch.size();
+  c->ring_reap_pos = pos;
+  c->outstanding.fetch_sub(n);
+  c->st_completed.fetch_add(n);
+  c->inflight_bytes.fetch_sub(pages * MS_PAGE_SIZE);
+  c->ring_desc.fetch_sub(pages);
+  c->ring_reqs.fetch_sub(n);
+  return true;
 }
 
 // Move queued small requests onto the ring (caller holds sched_mu): demand
@@ -863,12 +888,17 @@ bool ring_publish(ms_ctx* c) {
       gone.swap(c->ring_q);
       for (auto& p : c->ring_pf_q) gone.push_back(p);
       c->ring_pf_q.clear();
+      c->ring_q_n.store(0, std::memory_order_relaxed);
+      c->ring_pf_n.store(0, std::memory_order_relaxed);
     }
     for (auto& p : gone)
       complete_ticket_now(c, p.ticket_slot, MS_EDEVICE,
                           (uint32_t)(p.req.key & 0xffffffffu) - 1);
     return !gone.empty();
   }
+  if (c->ring_q_n.load(std::memory_order_relaxed) == 0 &&
+      c->ring_pf_n.load(std::memory_order_relaxed) == 0)
+    return false;
   ms_resident* r = c->ring.load(std::memory_order_relaxed);
   uint64_t published = 0;
   for (;;) {
@@ -886,6 +916,8 @@ bool ring_publish(ms_ctx* c) {
                                  q->front().req.n_pages)) {
         p = q->front();
         q->pop_front();
+        (q == &c->ring_q ? c->ring_q_n : c->ring_pf_n)
+            .store(q->size(), std::memory_order_relaxed);
         have = true;
       }
     }
@@ -1030,6 +1062,10 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
     c->st_eagain.fetch_add(1);
     return st;
   }
+  // the tickets are formed now: once a request is published it may finish
+  // and its slot be reused (a later generation) before this call returns
+  std::vector<ms_ticket> tk(n);
+  for (size_t i = 0; i < n; ++i) tk[i] = make_ticket(c, ts[i]);
   // Take a reference on every key under the key lock, re-checking that each
   // handle is still live, so that ms_key_destroy cannot slip in between.
   {
@@ -1053,34 +1089,46 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
   // On the ring stage a small request that nothing waits before, and that
   // fits the admission cap and the ring, is published by this thread at
   // once (a reservation is two atomic updates; the ring has its own lock);
-  // the others queue for the scheduler.
-  std::vector<Pending> direct;
+  // the others queue for the scheduler.  Whether anything waits is read
+  // from the queue sizes without the queue lock; once one of this call's
+  // requests queues, the rest queue behind it.
+  std::vector<Pending> direct, queued;
   ms_resident* ring =
       c->ring_mode ? c->ring.load(std::memory_order_acquire) : nullptr;
-  {
-    std::lock_guard<std::mutex> lk(c->q_mu);
-    for (size_t i = 0; i < n; ++i) {
-      Pending p;
-      p.req = reqs[i];
-      // store the resolved slot in the low word, generation unchanged
-      p.req.key = (reqs[i].key & 0xffffffff00000000ull) | (ks[i] + 1);
-      p.ticket_slot = ts[i];
-      p.prefetch = prefetch;
-      if (c->ring_mode && reqs[i].n_pages <= kRingMaxPages) {
-        const bool first = prefetch
-                               ? c->ring_q.empty() && c->ring_pf_q.empty() &&
-                                     c->ring_desc.load() < c->ring_workers / 2
-                               : c->ring_q.empty();
-        if (ring && first &&
-            reserve_admission(c, reqs[i].n_pages * MS_PAGE_SIZE,
-                              reqs[i].n_pages))
-          direct.push_back(p);
-        else
-          (prefetch ? c->ring_pf_q : c->ring_q).push_back(p);
-      } else {
-        (prefetch ? c->prefetch_q : c->demand_q).push_back(p);
+  bool ring_queued = false;
+  for (size_t i = 0; i < n; ++i) {
+    Pending p;
+    p.req = reqs[i];
+    // store the resolved slot in the low word, generation unchanged
+    p.req.key = (reqs[i].key & 0xffffffff00000000ull) | (ks[i] + 1);
+    p.ticket_slot = ts[i];
+    p.prefetch = prefetch;
+    if (c->ring_mode && reqs[i].n_pages <= kRingMaxPages) {
+      const bool nothing_waits =
+          !ring_queued && c->ring_q_n.load(std::memory_order_relaxed) == 0 &&
+          (!prefetch ||
+           (c->ring_pf_n.load(std::memory_order_relaxed) == 0 &&
+            c->ring_desc.load() < c->ring_workers / 2));
+      if (ring && nothing_waits &&
+          reserve_admission(c, reqs[i].n_pages * MS_PAGE_SIZE,
+                            reqs[i].n_pages)) {
+        direct.push_back(p);
+        continue;
       }
+      ring_queued = true;
     }
+    queued.push_back(p);
+  }
+  if (!queued.empty()) {
+    std::lock_guard<std::mutex> lk(c->q_mu);
+    for (const Pending& p : queued) {
+      if (c->ring_mode && p.req.n_pages <= kRingMaxPages)
+        (prefetch ? c->ring_pf_q : c->ring_q).push_back(p);
+      else
+        (prefetch ? c->prefetch_q : c->demand_q).push_back(p);
+    }
+    c->ring_q_n.store(c->ring_q.size(), std::memory_order_relaxed);
+    c->ring_pf_n.store(c->ring_pf_q.size(), std::memory_order_relaxed);
   }
   for (const Pending& p : direct) publish_reserved(c, ring, p);
   if (!direct.empty()) {
@@ -1111,7 +1159,7 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
   c->q_cv.notify_one();
   if (!prefetch) c->st_submitted.fetch_add(n);
   if (tickets_out)
-    for (size_t i = 0; i < n; ++i) tickets_out[i] = make_ticket(c, ts[i]);
+    for (size_t i = 0; i < n; ++i) tickets_out[i] = tk[i];
   return MS_OK;
 }
 
@@ -1280,6 +1328,13 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
                   cfg.cipher == MS_CIPHER_CHACHA);
   // one workgroup of 4 waves per compute unit: a poller and the workers
   c->ring_workers = (uint32_t)c->cu_count * ms::kWavesPerBlock - 1;
+  if (c->ring_mode) {
+    c->ring_meta.reset(new (std::nothrow) RingMeta[c->ring_depth]);
+    if (!c->ring_meta) {
+      delete c;
+      return MS_ENOMEM;
+    }
+  }
   c->resident_plain_wpc = ms::resident_waves_per_cu(
       ms::plain_kernel_fn(2, cfg.cipher, (int)cfg.rounds, ms::kNonceLinear));
   for (uint32_t u = 1; u <= 2; ++u)
@@ -1584,10 +1639,18 @@ ms_status ms_poll(ms_ctx* c, const ms_ticket* t, size_t n, int32_t* done,
       int32_t state = ts.state.load(std::memory_order_acquire);
       if (state == 0) {
         // a request on the ring is done once its positions' completion
-        // words say so, before the scheduler reaps it
+        // words say so, before the scheduler reaps it: at once if the
+        // reaper's completed prefix covers them, else from the words
         const ms_ticket rt = ts.ring.load(std::memory_order_acquire);
         ms_resident* r = c->ring.load(std::memory_order_acquire);
-        if (rt && r && ms_internal_ring_done(r, rt)) state = 1;
+        if (rt && r) {
+          uint64_t first = 0, count = 0;
+          ms_internal_ring_span(rt, &first, &count);
+          if (first + count <=
+                  c->ring_done_pos.load(std::memory_order_acquire) ||
+              ms_internal_ring_done(r, rt))
+            state = 1;
+        }
       }
       const uint32_t cur = ts.gen.load(std::memory_order_acquire);
       if (cur != g) {
@@ -1617,6 +1680,8 @@ ms_status ms_cancel_client(ms_ctx* c, uint32_t client, uint64_t* n_out) {
       }
       q->swap(keep);
     }
+    c->ring_q_n.store(c->ring_q.size(), std::memory_order_relaxed);
+    c->ring_pf_n.store(c->ring_pf_q.size(), std::memory_order_relaxed);
   }
   for (auto& p : gone)
     complete_ticket_now(c, p.ticket_slot, MS_ECANCELED,

@@ -81,5 +81,14 @@ ms_status ms_internal_ring_publish(ms_resident* r, uint32_t key_row,
                                    ms_ticket* ticket_out);
 // 1 once every position of a ring ticket has completed, else 0.
 int ms_internal_ring_done(ms_resident* r, ms_ticket t);
+// The ring positions [first, first + count) a ring ticket holds.
+void ms_internal_ring_span(ms_ticket t, uint64_t* first, uint64_t* count);
+// Positions handed out so far (every position below it has been published).
+uint64_t ms_internal_ring_published(ms_resident* r);
+// The first position p in [from, limit) whose completion word does not yet
+// say done (limit if there is none): with `from` a completed prefix of the
+// ring, the longer prefix, one read per position it passes.
+uint64_t ms_internal_ring_advance(ms_resident* r, uint64_t from,
+                                  uint64_t limit);
 bool ms_internal_ring_alive(ms_resident* r);
 void ms_internal_ring_stop(ms_resident* r);

@@ -555,6 +555,23 @@ int ms_internal_ring_done(ms_resident* r, ms_ticket t) {
   return 1;
 }
 
+void ms_internal_ring_span(ms_ticket t, uint64_t* first, uint64_t* count) {
+  *count = t & ((1ull << kTicketCountBits) - 1);
+  *first = (t >> kTicketCountBits) - 1;
+}
+
+uint64_t ms_internal_ring_published(ms_resident* r) {
+  return r->next_pos.load(std::memory_order_acquire);
+}
+
+uint64_t ms_internal_ring_advance(ms_resident* r, uint64_t from,
+                                  uint64_t limit) {
+  const uint64_t depth = r->cfg.ring_depth;
+  while (from < limit && load_acq(&r->completed[from & (depth - 1)]) >= from + 1)
+    ++from;
+  return from;
+}
+
 bool ms_internal_ring_alive(ms_resident* r) {
   return r && r->launched && !kernel_exited(r) &&
          !load_acq(&r->hctl->error);

@@ -186,6 +186,19 @@ __attribute__((weak)) ms_status ms_internal_ring_publish(
 __attribute__((weak)) int ms_internal_ring_done(ms_resident*, ms_ticket) {
   return 0;
 }
+__attribute__((weak)) void ms_internal_ring_span(ms_ticket, uint64_t* first,
+                                                 uint64_t* count) {
+  *first = 0;
+  *count = 0;
+}
+__attribute__((weak)) uint64_t ms_internal_ring_published(ms_resident*) {
+  return 0;
+}
+__attribute__((weak)) uint64_t ms_internal_ring_advance(ms_resident*,
+                                                        uint64_t from,
+                                                        uint64_t) {
+  return from;
+}
 __attribute__((weak)) bool ms_internal_ring_alive(ms_resident*) {
   return false;
 }
