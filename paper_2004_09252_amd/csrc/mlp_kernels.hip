@@ -296,55 +296,107 @@ __global__ void embed_gather_kernel(const uint16_t* __restrict__ E,
 }
 
 // dE[v][d] = sum over positions i, in increasing order, with ids[i] == v of
-// dx[i][d].  One wave per embedding row: it tests 64 positions at once and
-// adds the matching ones, found with a ballot, lowest first, so the sum has
-// a fixed order (deterministic) without scanning the positions one at a
-// time.  Loads are batched (512 ids, then up to 8 matching rows of dx, in
-// flight together) so the scan is not one memory round trip per step.
-__global__ __launch_bounds__(64) void embed_scatter_kernel(
+// dx[i][d] (ids clamped into [0, V) as the forward pass clamps them).
+// A workgroup of four waves owns four consecutive rows v, one per wave.  It
+// stages the ids, kScatterChunk at a time, into LDS as 16-bit values (V is
+// at most 65536) with all its threads, 32 loads per thread in flight; each
+// wave then scans the chunk for its row, 512 positions per step (eight LDS
+// reads in flight, one ballot that skips a step without a match, then one
+// per 64 positions in order), and appends the matching positions, lowest
+// first, to a list of its own in LDS.  When the list is full, and at
+// the end, the wave adds the dx rows it names with up to 16 loads in flight,
+// in list order.  So every row's sum runs over its positions in increasing
+// order, one after another, whatever the chunk and list sizes (the sum is
+// deterministic), and the ids are read from memory once per workgroup
+// instead of once per row.  Embedding widths above 64 take one pass per 64
+// columns.
+constexpr int kScatterChunk = 16384;
+constexpr int kScatterList = 256;
+static_assert(kScatterChunk % 512 == 0, "scan steps of 512 stay in the chunk");
+__global__ __launch_bounds__(256) void embed_scatter_kernel(
     const float* __restrict__ dx, const int32_t* __restrict__ ids, int B,
     int C, int D, int V, float* __restrict__ dE) {
-  const int v = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int n = B * C;
+  __shared__ uint16_t sid[kScatterChunk];
+  __shared__ int64_t plist[4][kScatterList];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int v = blockIdx.x * 4 + wave;  // >= V: stages ids, writes nothing
+  const int64_t n = (int64_t)B * C;
+  const unsigned long long below = (1ull << lane) - 1;
+  int64_t* list = plist[wave];
   for (int d0 = 0; d0 < D; d0 += 64) {
     const int d = d0 + lane;
     float acc = 0.f;
-    // ids 512 at a time: eight independent 64-id loads in flight, then the
-    // eight ballots in position order
-    for (int base = 0; base < n; base += 512) {
-      int id[8];
+    int cnt = 0;
+    // add the listed rows in list order, 16 loads in flight
+    auto flush = [&]() {
+      for (int t0 = 0; t0 < cnt; t0 += 16) {
+        float val[16];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int i = base + 64 * q + lane;
-        const int x = ids[i < n ? i : n - 1];
-        id[q] = i < n ? (x < 0 ? 0 : (x >= V ? V - 1 : x)) : -1;
+        for (int t = 0; t < 16; ++t)
+          val[t] = (t0 + t < cnt && d < D)
+                       ? dx[list[t0 + t] * D + d]
+                       : 0.f;
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+          if (t0 + t < cnt) acc += val[t];
       }
+      cnt = 0;
+    };
+    for (int64_t base = 0; base < n; base += kScatterChunk) {
+      const int len = (int)(n - base < kScatterChunk ? n - base : kScatterChunk);
+      __syncthreads();  // the previous chunk's scans are done
+      // 32 loads of each thread in flight before their stores
+      for (int j0 = 0; j0 < len; j0 += 256 * 32) {
+        int x[32];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        unsigned long long m = __ballot(id[q] == v);
-        // matches up to 8 at a time: their dx loads issued together, then
-        // added in ascending position, the same order as one by one
-        while (m) {
-          int pos[8];
-          int cnt = 0;
+        for (int q = 0; q < 32; ++q) {
+          const int j = j0 + 256 * q + (int)threadIdx.x;
+          x[q] = j < len ? ids[base + j] : 0;
+        }
 #pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            pos[t] = m ? base + 64 * q + __ffsll(m) - 1 : 0;
-            cnt += m ? 1 : 0;
-            m &= m - 1;
+        for (int q = 0; q < 32; ++q) {
+          const int j = j0 + 256 * q + (int)threadIdx.x;
+          if (j < len)
+            sid[j] = (uint16_t)(x[q] < 0 ? 0 : (x[q] >= V ? V - 1 : x[q]));
+        }
+      }
+      __syncthreads();
+      if (v < V) {
+        // 512 positions per step: eight LDS reads in flight, one ballot
+        // that skips the step when none matches, else one per 64 in order
+        for (int j0 = 0; j0 < len; j0 += 512) {
+          bool hit[8];
+          bool any = false;
+          // (j0 + 511 stays inside the chunk buffer, whose size is a
+          // multiple of 512: the reads need no guard, entries past len are
+          // masked out)
+          uint32_t sv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) sv[q] = sid[j0 + 64 * q + lane];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            hit[q] = (j0 + 64 * q + lane < len) & (sv[q] == (uint32_t)v);
+            any = any | hit[q];
           }
-          float val[8];
+          if (!__ballot(any)) continue;
 #pragma unroll
-          for (int t = 0; t < 8; ++t)
-            val[t] = (t < cnt && d < D) ? dx[(int64_t)pos[t] * D + d] : 0.f;
-#pragma unroll
-          for (int t = 0; t < 8; ++t)
-            if (t < cnt) acc += val[t];
+          for (int q = 0; q < 8; ++q) {
+            const unsigned long long m = __ballot(hit[q]);
+            if (!m) continue;
+            const int k = __popcll(m);
+            if (cnt + k > kScatterList) flush();
+            if (hit[q])
+              list[cnt + __popcll(m & below)] = base + j0 + 64 * q + lane;
+            cnt += k;
+          }
         }
       }
     }
-    if (d < D) dE[(int64_t)v * D + d] = acc;
+    if (v < V) {
+      flush();
+      if (d < D) dE[(int64_t)v * D + d] = acc;
+    }
   }
 }
 
@@ -786,8 +838,8 @@ ms_status ms_mlp_backward(const ms_mlp_shape* s, const uint16_t* P,
   g = gemm_args(w.dz1H, H, 0, P + off[1], H, 1, B, CD, H);
   g.outF = w.dxF; g.ldo = CD;
   if (gemm(g, w, st) != hipSuccess) return MS_EDEVICE;
-  hipLaunchKernelGGL(embed_scatter_kernel, dim3(V), dim3(64), 0, st, w.dxF,
-                     ids, B, s->context, s->embed, V, G + off[0]);
+  hipLaunchKernelGGL(embed_scatter_kernel, dim3((V + 3) / 4), dim3(256), 0,
+                     st, w.dxF, ids, B, s->context, s->embed, V, G + off[0]);
   return hipGetLastError() == hipSuccess ? MS_OK : MS_EDEVICE;
 }
 

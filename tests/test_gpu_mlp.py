@@ -205,6 +205,42 @@ def test_ragged_split_k_matches_reference_and_repeats_exactly():
     assert np.array_equal(pred.grads.cpu().numpy(), first.numpy())
 
 
+WIDE = dict(vocab=128, context=20, embed=96, hidden=64)
+
+
+def test_embedding_gradient_over_several_id_chunks():
+    """Batch 1000 x context 20 = 20000 ids: the embedding-gradient kernel
+    stages them in two chunks (16384, then a ragged 3616), and embed 96
+    takes two column passes (64, then a ragged 32).  Two rows collect 3000
+    contributions each, across both chunks (their position lists fill and
+    are added many times over), and one row none.  The gradients match the
+    reference, and a second pass is bit-identical."""
+    _note("embedding gradient shape %s batch 1000" % WIDE)
+    from paper_2004_09252_amd.predictor import Predictor
+    pred = Predictor(max_batch=1024, **WIDE)
+    rng = np.random.default_rng(23)
+    p = mlp_ref.init_params(rng, **WIDE)
+    pred.load_master(np.concatenate(
+        [p[k].reshape(-1) for k in mlp_ref.PARAMS]).astype(np.float32))
+    pb = {k: mlp_ref.bf16_round(v.astype(np.float32)) for k, v in p.items()}
+    B = 1000
+    ids = rng.integers(2, WIDE["vocab"] - 1, size=(B, WIDE["context"]))
+    ids[:300] = rng.integers(0, 2, size=(300, WIDE["context"]))
+    ids[-1, -1] = 0  # the last position of the ragged chunk
+    tgt = rng.integers(0, WIDE["vocab"], size=B)
+    pred.backward(ids, tgt)
+    first = pred.grads.cpu().clone()
+    _, g = mlp_ref.loss_and_grads(pb, ids, tgt, round_fn=mlp_ref.bf16_round,
+                                  grad_round_fn=mlp_ref.bf16_round)
+    gg = pred.unpack(first)
+    dE = gg["E"].numpy().reshape(WIDE["vocab"], WIDE["embed"])
+    assert not np.any(dE[WIDE["vocab"] - 1])
+    for k in mlp_ref.PARAMS:
+        _close(gg[k].numpy(), g[k], "grad " + k)
+    pred.backward(ids, tgt)
+    assert np.array_equal(pred.grads.cpu().numpy(), first.numpy())
+
+
 def test_topk_ragged_vocab_over_several_chunks():
     """A vocabulary of 2500 (three 1024-wide chunks, the last ragged), an
     excluded id, a row that is -inf but for one value, ties, and rows with
