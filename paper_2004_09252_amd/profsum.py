@@ -271,10 +271,11 @@ def resident(trace_db: str, fetch_db: str, write_db: str, sq_db: str,
                     "SQ_WAIT_ANY", "SQ_WAVE_CYCLES", "GRBM_GUI_ACTIVE")}
     lines = [
         "# rocprofv3 summary of the resident-key kernel on HBM pages",
-        "# trace command: " + cmd + " --kernel-trace --stats",
-        "# counter commands: the same with --pmc FETCH_SIZE, then "
-        "--pmc WRITE_SIZE, then --pmc SQ_INSTS_VALU SQ_WAVES SQ_BUSY_CYCLES "
-        "SQ_WAIT_ANY SQ_WAVE_CYCLES GRBM_GUI_ACTIVE",
+        "# trace command: " + cmd,
+        "# counter commands: the same with --kernel-trace --stats replaced "
+        "by --pmc FETCH_SIZE, then --pmc WRITE_SIZE, then --pmc "
+        "SQ_INSTS_VALU SQ_WAVES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAVE_CYCLES "
+        "GRBM_GUI_ACTIVE (one run each)",
         "# one dispatch spans the engine's life, idle polling included",
         "kernel: %s" % RESIDENT_KERNEL,
         "dispatches_traced: %d" % len(durs),
