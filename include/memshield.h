@@ -313,10 +313,19 @@ ms_status ms_process_batch_static(ms_ctx *ctx, const ms_request *reqs,
  * on its own streams, which do not wait for the caller's streams: a
  * request's source bytes (and nonce array) must be complete, and no other
  * work may still be writing its destination, when ms_submit is called
- * (e.g. synchronize the stream that produced them first).  A scheduler thread admits queued
- * requests into fused launches while the page bytes in flight stay within
- * admission_cap_bytes and a batch slot is free, so batches that arrive while
- * others run overlap on the device.  tickets_out[i] receives a ticket per
+ * (e.g. synchronize the stream that produced them first).  Admission keeps
+ * the page bytes in flight within admission_cap_bytes on either serving
+ * stage (ms_config.serve_stage):
+ *   - ring stage: a request of at most 1024 pages is published by the
+ *     submitting thread at once (one descriptor per page into the ring of a
+ *     resident kernel) when nothing waits and the ring has free positions;
+ *     otherwise it waits in its client's queue (ms_request.client), and the
+ *     queues are published round robin, one request per client per turn,
+ *     each client's requests in submission order;
+ *   - launch stage (and requests above 1024 pages): a scheduler thread
+ *     forms fused launches while a batch slot is free, so batches that
+ *     arrive while others run overlap on the device.
+ * tickets_out[i] receives a ticket per
  * request.  All-or-nothing: on any error no request of the call is queued.
  * Errors: MS_EINVAL, MS_ENOKEY, MS_EAGAIN (queue full), MS_ECLOSED.
  * Thread-safe: any number of threads may submit and poll at once.

@@ -25,6 +25,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <unordered_map>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -96,6 +97,56 @@ struct Pending {
   ms_request req;
   uint32_t ticket_slot;
   bool prefetch;
+};
+
+// Demand requests waiting for the ring serving stage: one FIFO per client,
+// served round robin.  A client with a backlog takes one turn per round, so
+// a burst from one client delays another client's request by one request
+// per waiting client, not by the whole burst; each client's own requests
+// keep their order.
+struct ClientQueues {
+  std::unordered_map<uint32_t, std::deque<Pending>> fifo;
+  std::deque<uint32_t> turn;  // clients with a non-empty FIFO, next first
+  size_t n = 0;
+
+  bool empty() const { return n == 0; }
+  size_t size() const { return n; }
+  void push(const Pending& p) {
+    std::deque<Pending>& d = fifo[p.req.client];
+    if (d.empty()) turn.push_back(p.req.client);
+    d.push_back(p);
+    ++n;
+  }
+  // The request whose turn it is (the queues must not be empty).
+  const Pending& front() { return fifo[turn.front()].front(); }
+  // Take that request; its client goes to the back of the round.
+  void pop_front() {
+    const uint32_t cl = turn.front();
+    turn.pop_front();
+    std::deque<Pending>& d = fifo[cl];
+    d.pop_front();
+    --n;
+    if (d.empty())
+      fifo.erase(cl);
+    else
+      turn.push_back(cl);
+  }
+  // Move one client's requests (all of them if `all`) into `out`.
+  void take(uint32_t client, bool all, std::vector<Pending>* out) {
+    for (auto it = fifo.begin(); it != fifo.end();) {
+      if (all || it->first == client) {
+        for (const Pending& p : it->second) out->push_back(p);
+        n -= it->second.size();
+        it = fifo.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    std::deque<uint32_t> keep;
+    for (uint32_t cl : turn)
+      if (fifo.count(cl)) keep.push_back(cl);
+    turn.swap(keep);
+  }
 };
 
 struct TicketSlot {
@@ -183,7 +234,7 @@ struct ms_ctx {
   std::deque<Pending> demand_q;
   std::deque<Pending> prefetch_q;
   // ring serving stage: requests of at most kRingMaxPages pages
-  std::deque<Pending> ring_q;
+  ClientQueues ring_q;
   std::deque<Pending> ring_pf_q;
   // their sizes, written under q_mu and read without it, so that a
   // submission or a scheduler pass finds empty queues without the lock
@@ -882,10 +933,10 @@ bool ring_publish(ms_ctx* c) {
   bool any = false;
   if (ensure_ring(c) != MS_OK) {
     // no ring: fail what is queued for it
-    std::deque<Pending> gone;
+    std::vector<Pending> gone;
     {
       std::lock_guard<std::mutex> lk(c->q_mu);
-      gone.swap(c->ring_q);
+      c->ring_q.take(0, true, &gone);
       for (auto& p : c->ring_pf_q) gone.push_back(p);
       c->ring_pf_q.clear();
       c->ring_q_n.store(0, std::memory_order_relaxed);
@@ -906,19 +957,25 @@ bool ring_publish(ms_ctx* c) {
     bool have = false;
     {
       std::lock_guard<std::mutex> lk(c->q_mu);
-      std::deque<Pending>* q = nullptr;
-      if (!c->ring_q.empty())
-        q = &c->ring_q;
-      else if (!c->ring_pf_q.empty() &&
-               c->ring_desc.load() < c->ring_workers / 2)
-        q = &c->ring_pf_q;
-      if (q && reserve_admission(c, q->front().req.n_pages * MS_PAGE_SIZE,
-                                 q->front().req.n_pages)) {
-        p = q->front();
-        q->pop_front();
-        (q == &c->ring_q ? c->ring_q_n : c->ring_pf_n)
-            .store(q->size(), std::memory_order_relaxed);
-        have = true;
+      if (!c->ring_q.empty()) {
+        const Pending& f = c->ring_q.front();
+        if (reserve_admission(c, f.req.n_pages * MS_PAGE_SIZE,
+                              f.req.n_pages)) {
+          p = f;
+          c->ring_q.pop_front();
+          c->ring_q_n.store(c->ring_q.size(), std::memory_order_relaxed);
+          have = true;
+        }
+      } else if (!c->ring_pf_q.empty() &&
+                 c->ring_desc.load() < c->ring_workers / 2) {
+        const Pending& f = c->ring_pf_q.front();
+        if (reserve_admission(c, f.req.n_pages * MS_PAGE_SIZE,
+                              f.req.n_pages)) {
+          p = f;
+          c->ring_pf_q.pop_front();
+          c->ring_pf_n.store(c->ring_pf_q.size(), std::memory_order_relaxed);
+          have = true;
+        }
       }
     }
     if (!have) break;
@@ -1122,8 +1179,10 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
   if (!queued.empty()) {
     std::lock_guard<std::mutex> lk(c->q_mu);
     for (const Pending& p : queued) {
-      if (c->ring_mode && p.req.n_pages <= kRingMaxPages)
-        (prefetch ? c->ring_pf_q : c->ring_q).push_back(p);
+      if (c->ring_mode && p.req.n_pages <= kRingMaxPages && prefetch)
+        c->ring_pf_q.push_back(p);
+      else if (c->ring_mode && p.req.n_pages <= kRingMaxPages)
+        c->ring_q.push(p);
       else
         (prefetch ? c->prefetch_q : c->demand_q).push_back(p);
     }
@@ -1671,8 +1730,8 @@ ms_status ms_cancel_client(ms_ctx* c, uint32_t client, uint64_t* n_out) {
   std::vector<Pending> gone;
   {
     std::lock_guard<std::mutex> lk(c->q_mu);
-    for (auto* q : {&c->demand_q, &c->prefetch_q, &c->ring_q,
-                    &c->ring_pf_q}) {
+    c->ring_q.take(client, false, &gone);
+    for (auto* q : {&c->demand_q, &c->prefetch_q, &c->ring_pf_q}) {
       std::deque<Pending> keep;
       for (auto& p : *q) {
         if (p.req.client == client) gone.push_back(p);

@@ -409,6 +409,75 @@ def test_ring_requests_overlap_a_running_launch(ms):
         eng.close()
 
 
+def test_ring_stage_serves_clients_round_robin(ms):
+    """On the ring stage, requests that wait for ring positions queue per
+    client and are published round robin.  Client A submits a burst of 160
+    requests of 1024 pages (163,840 pages against a ring of 65,536
+    positions, so most of the burst waits); client B then submits 8
+    one-page requests.  B's requests take turns with A's, so all of them
+    finish while a quarter or more of A's burst is still pending (in one
+    FIFO they would finish after all of it).  Every output equals the
+    oracle (a sample of A's, all of B's)."""
+    _note("ring stage round robin: burst of 160 x 1024 pages + 8 x 1 page")
+    import torch
+    eng = ms.Engine(0, serve_stage=ms.MS_SERVE_STAGE_RING)
+    try:
+        rng = np.random.default_rng(49)
+        kb = [rng.bytes(32) for _ in range(2)]
+        keys = [eng.key_load(k) for k in kb]
+        na, pa, nb = 160, 1024, 8
+        a_src = torch.randint(0, 256, (na * pa * 4096,), dtype=torch.uint8,
+                              device="cuda")
+        a_dst = torch.zeros_like(a_src)
+        b_host = workloads.random_pages(rng, nb)
+        b_src = torch.from_numpy(b_host.reshape(-1).copy()).to("cuda")
+        b_dst = torch.zeros_like(b_src)
+        torch.cuda.synchronize()
+        t0 = eng.submit([ms.request(keys[1], b_src, b_dst, 1,
+                                    ms.linear_nonce(0, 1, 9))])
+        assert eng.poll(t0, timeout_s=30)[0] == 0   # the ring is up
+        ta = eng.submit([ms.request(keys[0], a_src, a_dst, pa,
+                                    ms.linear_nonce(pa * i, 1, 1), client=0,
+                                    src_offset_pages=pa * i,
+                                    dst_offset_pages=pa * i)
+                         for i in range(na)])
+        tb = eng.submit([ms.request(keys[1], b_src, b_dst, 1,
+                                    ms.linear_nonce(i, 1, 2), client=1,
+                                    src_offset_pages=i, dst_offset_pages=i)
+                         for i in range(nb)])
+        tickets = list(ta) + list(tb)
+        seen = [None] * len(tickets)
+        it = 0
+        deadline = time.time() + 60
+        while any(x is None for x in seen):
+            assert time.time() < deadline, "requests did not finish"
+            st, d = ms.ms_poll(eng.ctx, tickets, 0)
+            assert st in (0, ms.MS_ETIMEDOUT)
+            for k, v in enumerate(d):
+                assert v >= 0, (k, v)
+                if v == 1 and seen[k] is None:
+                    seen[k] = it
+            it += 1
+        assert eng.poll(tickets, timeout_s=10)[0] == 0
+        b_last = max(seen[na:])
+        a_done = sum(1 for x in seen[:na] if x <= b_last)
+        assert a_done <= 3 * na // 4, (a_done, b_last, it)
+        got = b_dst.cpu().numpy().reshape(nb, 4096)
+        for i in range(nb):
+            want = oracle.cipher_pages(kb[1], oracle.nonces_linear(
+                1, i, 1, 2), b_host[i:i + 1])
+            assert np.array_equal(got[i:i + 1], want), i
+        for i in (0, 1, na // 2, na - 1):
+            s0 = pa * i * 4096
+            src_h = a_src[s0:s0 + pa * 4096].cpu().numpy().reshape(pa, 4096)
+            want = oracle.cipher_pages(kb[0], oracle.nonces_linear(
+                pa, pa * i, 1, 1), src_h, threads=HOST_THREADS)
+            got_a = a_dst[s0:s0 + pa * 4096].cpu().numpy().reshape(pa, 4096)
+            assert np.array_equal(got_a, want), i
+    finally:
+        eng.close()
+
+
 def test_ring_stage_refused_for_salsa20(ms):
     st, ctx = ms.ms_init(0, _cfg(ms, cipher=ms.MS_CIPHER_SALSA,
                                  serve_stage=ms.MS_SERVE_STAGE_RING))
