@@ -1064,7 +1064,13 @@ def main():
                                        / MI355X_HBM_BYTES, 4)},
     }
     log("calibration probes")
-    line["calibration"] = calibrate(ms, torch)
+    line["calibration"] = cal = calibrate(ms, torch)
+    # the same achieved rates against the ceilings measured on this machine
+    rl = line["roofline"]
+    rl["frac_of_measured_valu_peak"] = round(
+        rl["achieved"] / cal["valu_int32_Tops"], 4)
+    rl["hbm_frac_of_measured_copy"] = round(
+        rl["hbm_GBps_algorithmic"] / cal["copy_hbm_GBps"], 4)
     if not args.no_variants:
         log("reduced-round variants")
         line["cipher_variants"] = run_variants(args, ms, torch, b)
