@@ -153,9 +153,8 @@ typedef struct ms_config {
  * launches.  The kernel starts with the first submission (about one
  * workgroup of 4 waves on every compute unit) and runs until ms_shutdown.
  * Prefetch hints enter the ring only while no demand request waits and at
- * most half of the workers hold work.  The ring runs ChaCha only.
- * MS_SERVE_STAGE_AUTO: the ring for a ChaCha context, launches otherwise.
- * ms_init returns MS_ENOTSUP for MS_SERVE_STAGE_RING with Salsa20.
+ * most half of the workers hold work.  The ring runs the context's cipher
+ * and round count.  MS_SERVE_STAGE_AUTO: the ring.
  */
 #define MS_SERVE_STAGE_AUTO 0u
 #define MS_SERVE_STAGE_LAUNCH 1u
@@ -167,9 +166,9 @@ typedef struct ms_config {
  * MS_CIPHER_SALSA is Salsa20 (Bernstein 2008) with `rounds` rounds over the
  * same page interface: for page nonce N (12 bytes) block j of the page is
  * the Salsa20 block with the 64-bit nonce N[0..7] and the 64-bit block
- * counter LE32(N[8..11]) * 2^32 + j.  The resident-key engine
- * (memshield_resident.h) runs ChaCha only: with a Salsa20 context it
- * returns MS_ENOTSUP.
+ * counter LE32(N[8..11]) * 2^32 + j.  Every path runs it: plain and
+ * batched launches, host-page modes, both serving stages and the
+ * resident-key engine (memshield_resident.h).
  */
 #define MS_CIPHER_CHACHA 0u
 #define MS_CIPHER_SALSA 1u

@@ -72,14 +72,13 @@ typedef struct ms_resident_config {
 void ms_resident_config_default(ms_resident_config *cfg);
 
 /*
- * Start a resident-key engine on ctx's device with ctx's round count.  `key`
- * is 32 bytes, or NULL to draw them with getrandom(2) straight into the
- * library's pinned staging buffer (the key is then known to no one).  Waits
- * until every worker holds the key and its memory copies are wiped.  The
- * engine runs ChaCha: MS_ENOTSUP for a context whose cipher is
- * MS_CIPHER_SALSA.  Errors: MS_EINVAL, MS_ENOMEM, MS_EDEVICE, MS_ENOTSUP,
- * MS_ETIMEDOUT (the kernel did not report ready within 10 s; it is
- * stopped).
+ * Start a resident-key engine on ctx's device with ctx's cipher and round
+ * count (ms_config.cipher, .rounds).  `key` is 32 bytes, or NULL to draw
+ * them with getrandom(2) straight into the library's pinned staging buffer
+ * (the key is then known to no one).  Waits until every worker holds the
+ * key and its memory copies are wiped.  Errors: MS_EINVAL, MS_ENOMEM,
+ * MS_EDEVICE, MS_ETIMEDOUT (the kernel did not report ready within 10 s; it
+ * is stopped).
  */
 ms_status ms_resident_start(ms_ctx *ctx, const ms_resident_config *cfg,
                             const uint8_t *key, ms_resident **out);

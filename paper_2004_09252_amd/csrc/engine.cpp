@@ -1349,9 +1349,6 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
   if (cfg.cipher != MS_CIPHER_CHACHA && cfg.cipher != MS_CIPHER_SALSA)
     return MS_EINVAL;
   if (cfg.serve_stage > MS_SERVE_STAGE_RING) return MS_EINVAL;
-  // the ring's kernel runs ChaCha only
-  if (cfg.serve_stage == MS_SERVE_STAGE_RING && cfg.cipher != MS_CIPHER_CHACHA)
-    return MS_ENOTSUP;
   if (cfg.queue_depth == 0 || (cfg.queue_depth & (cfg.queue_depth - 1)) ||
       cfg.queue_depth > (1u << 24))
     return MS_EINVAL;
@@ -1382,9 +1379,7 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
   }
   c->cu_count = prop.multiProcessorCount;
   c->arch = prop.gcnArchName;
-  c->ring_mode = cfg.serve_stage == MS_SERVE_STAGE_RING ||
-                 (cfg.serve_stage == MS_SERVE_STAGE_AUTO &&
-                  cfg.cipher == MS_CIPHER_CHACHA);
+  c->ring_mode = cfg.serve_stage != MS_SERVE_STAGE_LAUNCH;
   // one workgroup of 4 waves per compute unit: a poller and the workers
   c->ring_workers = (uint32_t)c->cu_count * ms::kWavesPerBlock - 1;
   if (c->ring_mode) {

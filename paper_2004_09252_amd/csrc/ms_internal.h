@@ -67,7 +67,7 @@ void ms_internal_resident_stop_all(ms_ctx* c);
 // that holds no key of its own and reads, for each descriptor, the row of
 // the context's device key table (`key_table`, `table_rows` rows) the
 // descriptor names.  Not registered with the context: its owner stops it
-// with ms_internal_ring_stop.  ChaCha only.
+// with ms_internal_ring_stop.  It runs the context's cipher and rounds.
 ms_status ms_internal_ring_start(ms_ctx* c, const ms_resident_config* cfg,
                                  const uint32_t* key_table,
                                  uint32_t table_rows, ms_resident** out);

@@ -80,10 +80,13 @@ struct RkArgs {
 };
 
 // Kernel entry points (plain C names in the separately built code object),
-// one per round count; launched as (n_workers + 1) waves in 256-thread
+// one per cipher and round count; launched as (n_workers + 1) waves in 256-thread
 // workgroups (the group segment size comes from the code object).
 constexpr const char* kResidentKernel20 = "ms_resident_pages_r20.kd";
 constexpr const char* kResidentKernel12 = "ms_resident_pages_r12.kd";
 constexpr const char* kResidentKernel8 = "ms_resident_pages_r8.kd";
+constexpr const char* kResidentSalsa20 = "ms_resident_pages_s20.kd";
+constexpr const char* kResidentSalsa12 = "ms_resident_pages_s12.kd";
+constexpr const char* kResidentSalsa8 = "ms_resident_pages_s8.kd";
 
 }  // namespace ms

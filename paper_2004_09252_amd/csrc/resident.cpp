@@ -183,18 +183,20 @@ hsa_status_t match_agent(hsa_agent_t a, void* data) {
   return HSA_STATUS_SUCCESS;
 }
 
-const char* kernel_symbol(int rounds) {
+const char* kernel_symbol(uint32_t cipher, int rounds) {
+  const bool salsa = cipher == MS_CIPHER_SALSA;
   switch (rounds) {
-    case 20: return ms::kResidentKernel20;
-    case 12: return ms::kResidentKernel12;
-    case 8: return ms::kResidentKernel8;
+    case 20: return salsa ? ms::kResidentSalsa20 : ms::kResidentKernel20;
+    case 12: return salsa ? ms::kResidentSalsa12 : ms::kResidentKernel12;
+    case 8: return salsa ? ms::kResidentSalsa8 : ms::kResidentKernel8;
   }
   return nullptr;
 }
 
 // Load the embedded code object on the context's GPU agent, create the
 // engine's queue and completion signal, and write the dispatch packet.
-ms_status dispatch(ms_resident* r, const ms::RkArgs& args, int rounds) {
+ms_status dispatch(ms_resident* r, const ms::RkArgs& args, uint32_t cipher,
+                   int rounds) {
   hipDeviceProp_t prop;
   if (!hip_ok(hipGetDeviceProperties(&prop, r->device))) return MS_EDEVICE;
   if (hsa_init() != HSA_STATUS_SUCCESS) return MS_EDEVICE;
@@ -219,7 +221,7 @@ ms_status dispatch(ms_resident* r, const ms::RkArgs& args, int rounds) {
           HSA_STATUS_SUCCESS ||
       hsa_executable_freeze(r->exe, nullptr) != HSA_STATUS_SUCCESS)
     return MS_EDEVICE;
-  const char* name = kernel_symbol(rounds);
+  const char* name = kernel_symbol(cipher, rounds);
   hsa_executable_symbol_t sym;
   uint64_t kernel_object = 0;
   uint32_t kernarg_size = 0, group_size = 0, private_size = 0;
@@ -343,8 +345,7 @@ ms_status start_engine(ms_ctx* c, const ms_resident_config* cfg_in,
   ms_resident_config cfg;
   if (cfg_in) cfg = *cfg_in; else ms_resident_config_default(&cfg);
   const int rounds = (int)ms_internal_config(c).rounds;
-  // the resident kernel holds the ChaCha rounds only
-  if (ms_internal_config(c).cipher != MS_CIPHER_CHACHA) return MS_ENOTSUP;
+  const uint32_t cipher = ms_internal_config(c).cipher;
   if (cfg.ring_depth < 16 || cfg.ring_depth > (1u << 20) ||
       (cfg.ring_depth & (cfg.ring_depth - 1)) || cfg.desc_pages == 0 ||
       cfg.desc_pages > 1024 || cfg.idle_limit_ms > 3600u * 1000u)
@@ -463,7 +464,7 @@ ms_status start_engine(ms_ctx* c, const ms_resident_config* cfg_in,
   a.inv_step = ms::share_stride_inverse(r->workers);
   a.table_rows = table_rows;
   a.key_table = table;
-  st = dispatch(r, a, rounds);
+  st = dispatch(r, a, cipher, rounds);
   if (st) {
     release(r);
     return st;

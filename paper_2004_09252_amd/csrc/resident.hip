@@ -134,7 +134,7 @@ __device__ void poll_host(const RkArgs& a, uint32_t lane) {
 // Cipher n_pages consecutive pages from `src` to `dst` (GPU-visible
 // addresses) with key `kk`.  ARRAY: page p's nonce is the 12 bytes at nb +
 // 12p (every lane reads them); otherwise it is LE64(nb + p*ns) || tag.
-template <int ROUNDS, bool ARRAY>
+template <uint32_t CIPHER, int ROUNDS, bool ARRAY>
 __device__ __forceinline__ void cipher_run(const uint32_t (&kk)[8],
                                            uint64_t src, uint64_t dst,
                                            uint64_t nb, uint64_t ns,
@@ -162,7 +162,8 @@ __device__ __forceinline__ void cipher_run(const uint32_t (&kk)[8],
       n[2] = tag;
     }
     uint32_t ks[16];
-    keystream<ROUNDS>(ks, kk, n, lane);  // block `lane` = bytes 64*lane..
+    // block `lane` = bytes 64*lane..
+    cipher_keystream<CIPHER, ROUNDS>(ks, kk, n, lane);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       lds[lds_slot(lane * 4 + q)] =
@@ -200,7 +201,7 @@ __device__ __forceinline__ void cipher_run(const uint32_t (&kk)[8],
 // a page count outside 1..max_pages, a key index outside the engine's keys
 // or an unknown nonce kind is not touched and raises `error`.  `k` is the
 // key of a one-key engine; `keytab` the LDS key table of a many-key engine.
-template <int ROUNDS>
+template <uint32_t CIPHER, int ROUNDS>
 __device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
                           const uint32_t* keytab, uint64_t pos, uint4* lds,
                           uint32_t lane) {
@@ -251,9 +252,11 @@ __device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
     for (int i = 0; i < 8; ++i) asm volatile("" : "+s"(kk[i]) : : "memory");
     // the nonce kind is decided once per descriptor, outside the page loop
     if (kind == 0)
-      cipher_run<ROUNDS, true>(kk, src, dst, nb, ns, tag, n_pages, lds, lane);
+      cipher_run<CIPHER, ROUNDS, true>(kk, src, dst, nb, ns, tag, n_pages,
+                                       lds, lane);
     else
-      cipher_run<ROUNDS, false>(kk, src, dst, nb, ns, tag, n_pages, lds, lane);
+      cipher_run<CIPHER, ROUNDS, false>(kk, src, dst, nb, ns, tag, n_pages,
+                                        lds, lane);
   }
   // The page stores are complete before the completion word is written.
   // Every global store of this worker since its last completion word is a
@@ -267,7 +270,7 @@ __device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
   st_sys64(&a.completed[pos & a.ring_mask], pos + 1);
 }
 
-template <int ROUNDS>
+template <uint32_t CIPHER, int ROUNDS>
 __device__ void serve_ring(const RkArgs& a, const uint32_t* keytab,
                            uint4* lds, uint32_t lane, uint32_t worker) {
   uint32_t k[8];
@@ -316,11 +319,11 @@ __device__ void serve_ring(const RkArgs& a, const uint32_t* keytab,
       else
         __builtin_amdgcn_s_sleep(64);
     }
-    serve_one<ROUNDS>(a, k, keytab, pos, lds, lane);
+    serve_one<CIPHER, ROUNDS>(a, k, keytab, pos, lds, lane);
   }
 }
 
-template <int ROUNDS>
+template <uint32_t CIPHER, int ROUNDS>
 __device__ __forceinline__ void resident_pages(const RkArgs& a) {
   __shared__ uint4 lds[kWavesPerBlock][256];
   __shared__ uint32_t keytab[kRkMaxKeys * 8];
@@ -342,24 +345,23 @@ __device__ __forceinline__ void resident_pages(const RkArgs& a) {
     return;
   }
   if (gw > a.n_workers) return;
-  serve_ring<ROUNDS>(a, keytab, lds[w], lane, gw - 1);
+  serve_ring<CIPHER, ROUNDS>(a, keytab, lds[w], lane, gw - 1);
 }
 
 }  // namespace
 }  // namespace ms
 
-// Entry points by round count.  This file is built as its own code object
-// and dispatched by resident.cpp on a private HSA queue, so the names are
-// plain C symbols.
-extern "C" __global__ __launch_bounds__(ms::kBlockThreads) void
-ms_resident_pages_r20(ms::RkArgs a) {
-  ms::resident_pages<20>(a);
-}
-extern "C" __global__ __launch_bounds__(ms::kBlockThreads) void
-ms_resident_pages_r12(ms::RkArgs a) {
-  ms::resident_pages<12>(a);
-}
-extern "C" __global__ __launch_bounds__(ms::kBlockThreads) void
-ms_resident_pages_r8(ms::RkArgs a) {
-  ms::resident_pages<8>(a);
-}
+// Entry points by cipher and round count (r: ChaCha, s: Salsa20).  This
+// file is built as its own code object and dispatched by resident.cpp on a
+// private HSA queue, so the names are plain C symbols.
+#define MS_RESIDENT_ENTRY(NAME, CIPHER, ROUNDS)                       \
+  extern "C" __global__ __launch_bounds__(ms::kBlockThreads) void NAME( \
+      ms::RkArgs a) {                                                  \
+    ms::resident_pages<CIPHER, ROUNDS>(a);                             \
+  }
+MS_RESIDENT_ENTRY(ms_resident_pages_r20, ms::kCipherChaCha, 20)
+MS_RESIDENT_ENTRY(ms_resident_pages_r12, ms::kCipherChaCha, 12)
+MS_RESIDENT_ENTRY(ms_resident_pages_r8, ms::kCipherChaCha, 8)
+MS_RESIDENT_ENTRY(ms_resident_pages_s20, ms::kCipherSalsa, 20)
+MS_RESIDENT_ENTRY(ms_resident_pages_s12, ms::kCipherSalsa, 12)
+MS_RESIDENT_ENTRY(ms_resident_pages_s8, ms::kCipherSalsa, 8)

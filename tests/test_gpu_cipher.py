@@ -375,15 +375,6 @@ def test_salsa20_bulk_1gib_sampled(ms):
         e.close()
 
 
-def test_salsa20_context_refuses_resident_engine(ms):
-    e = ms.Engine(0, cipher=ms.MS_CIPHER_SALSA)
-    try:
-        st, h = ms.ms_resident_start(e.ctx, None, bytes(32))
-        assert st == ms.MS_ENOTSUP and not h
-    finally:
-        e.close()
-
-
 def test_plain_launch_info_names_the_launch(ms, eng):
     """ms_plain_launch_info describes what a call launches: the kernel's
     template arguments, one launch per 2^24 pages, a grid of the resident

@@ -384,6 +384,48 @@ def test_reduced_round_resident_kernels(ms, rounds):
         e.close()
 
 
+@pytest.mark.parametrize("rounds", [20, 12, 8])
+def test_salsa20_resident_kernels(ms, rounds):
+    """A Salsa20 context's engine dispatches the Salsa20 kernel of its round
+    count: host pages with one key in registers, and device pages with two
+    keys from the key table, both equal to the Salsa20 oracle."""
+    _note("resident salsa20 rounds=%d" % rounds)
+    import torch
+    rng = np.random.default_rng(60 + rounds)
+    key_b = [rng.bytes(32), rng.bytes(32)]
+    n = 37
+    data = workloads.random_pages(rng, n)
+    e = ms.Engine(0, cipher=ms.MS_CIPHER_SALSA, rounds=rounds)
+    try:
+        buf = e.host_alloc(n * 4096)
+        buf.array[:] = data.reshape(-1)
+        r = e.resident(key=key_b[0], workers=32, idle_limit_ms=IDLE_MS)
+        try:
+            r.wait([r.submit(buf, buf, ms.linear_nonce(BASE, STRIDE, TAG))])
+        finally:
+            r.stop()
+        want = [oracle.cipher_pages(
+            k, oracle.nonces_linear(n, BASE, STRIDE, TAG), data,
+            rounds=rounds, cipher="salsa") for k in key_b]
+        assert np.array_equal(buf.array.reshape(n, 4096), want[0])
+        buf.free()
+        handles = [e.key_load(k) for k in key_b]
+        src = _dev(torch, data)
+        out = [torch.zeros_like(src) for _ in key_b]
+        r = e.resident(keys=handles, workers=64, desc_pages=1,
+                       idle_limit_ms=IDLE_MS)
+        try:
+            r.wait([r.submit(src, o, ms.linear_nonce(BASE, STRIDE, TAG),
+                             key_index=i) for i, o in enumerate(out)])
+        finally:
+            r.stop()
+        for i, o in enumerate(out):
+            assert np.array_equal(o.cpu().numpy().reshape(n, 4096),
+                                  want[i]), i
+    finally:
+        e.close()
+
+
 def _dev(torch, data):
     return torch.from_numpy(data.reshape(-1).copy()).to("cuda")
 

@@ -478,24 +478,15 @@ def test_ring_stage_serves_clients_round_robin(ms):
         eng.close()
 
 
-def test_ring_stage_refused_for_salsa20(ms):
-    st, ctx = ms.ms_init(0, _cfg(ms, cipher=ms.MS_CIPHER_SALSA,
-                                 serve_stage=ms.MS_SERVE_STAGE_RING))
-    assert st == ms.MS_ENOTSUP and ctx.value is None
-
-
-def _cfg(ms, **kw):
-    c = ms.ms_config_default()
-    for k, v in kw.items():
-        setattr(c, k, v)
-    return c
-
-
-def test_salsa20_context_serves_through_launches(ms):
-    """A Salsa20 context's submissions (default stage) run on the fused
-    launches and equal the Salsa20 oracle."""
-    _note("salsa20 served")
-    eng = ms.Engine(0, cipher=ms.MS_CIPHER_SALSA)
+@STAGES
+@pytest.mark.parametrize("rounds", [20, 8])
+def test_salsa20_context_serves_on_both_stages(ms, stage, rounds):
+    """A Salsa20 context's submissions run on either serving stage (the
+    ring's resident kernel runs the context's cipher and rounds) and equal
+    the Salsa20 oracle request by request."""
+    _note("salsa20/%d served, stage %d" % (rounds, stage))
+    eng = ms.Engine(0, cipher=ms.MS_CIPHER_SALSA, rounds=rounds,
+                    serve_stage=stage)
     try:
         r = _Reqs(ms, eng, seed=49, n=20, max_pages=16)
         t = eng.submit([r.req(i, r.dst_a) for i in range(20)])
@@ -508,7 +499,8 @@ def test_salsa20_context_serves_through_launches(ms):
             want = oracle.cipher_pages(
                 r.kbytes[r.client[i]],
                 oracle.nonces_linear(n, int(r.va[i]), 4096, int(r.pid[i])),
-                r.host[s0:e0].reshape(n, 4096), cipher="salsa").reshape(-1)
+                r.host[s0:e0].reshape(n, 4096), rounds=rounds,
+                cipher="salsa").reshape(-1)
             assert np.array_equal(r.slice(r.dst_a, i), want), i
     finally:
         eng.close()

@@ -46,23 +46,25 @@ def test_no_scalar_memory_writes(src, tmp_path):
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not present")
 def test_resident_key_loads_bypass_scalar_cache(tmp_path):
     text = _asm("resident.hip", tmp_path)
-    body = text[text.index("ms_resident_pages_r20:"):]
-    body = body[:body.index(".Lfunc_end")]
-    # the eight key words: system-scope vector loads, then readfirstlane
-    by_base = {}
-    for base, off in re.findall(r"global_load_dword v\d+, v\d+, "
-                                r"(s\[\d+:\d+\])(?: offset:(\d+))? sc0 sc1",
-                                body):
-        by_base.setdefault(base, set()).add(int(off or 0))
-    key = set(range(0, 32, 4))
-    assert any(key <= offs for offs in by_base.values()), by_base
+    for name in ("ms_resident_pages_r20:", "ms_resident_pages_s20:"):
+        body = text[text.index(name):]
+        body = body[:body.index(".Lfunc_end")]
+        # the eight key words: system-scope vector loads, then readfirstlane
+        by_base = {}
+        for base, off in re.findall(r"global_load_dword v\d+, v\d+, "
+                                    r"(s\[\d+:\d+\])(?: offset:(\d+))? "
+                                    r"sc0 sc1", body):
+            by_base.setdefault(base, set()).add(int(off or 0))
+        key = set(range(0, 32, 4))
+        assert any(key <= offs for offs in by_base.values()), (name, by_base)
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not present")
 def test_resident_loops_are_wave_uniform(tmp_path):
     text = _asm("resident.hip", tmp_path)
-    for rounds in (20, 12, 8):
-        name = "ms_resident_pages_r%d:" % rounds
+    for name in ["ms_resident_pages_%s%d:" % (c, r)
+                 for c in "rs" for r in (20, 12, 8)]:
+        rounds = name
         body = text[text.index(name):]
         body = body[:body.index(".Lfunc_end")]
         assert "s_cbranch_execnz" not in body, rounds
