@@ -708,10 +708,23 @@ def run_serving(args, ms, torch):
                 ("plain", ms.MS_SERVE_PLAIN, eng, ks),
                 ("resident", ms.MS_SERVE_RESIDENT, eng, ks)):
             log("sweep %s %d req/s" % (name, rate))
+            before = e.stats()
             res, _ = serving.run(e, ls, kk, src, dst, mode)
+            after = e.stats()
             row[name + "_GBps"] = round(res.data_gbps, 2)
             row[name + "_p50_us"] = round(res.p50_us, 1)
             row[name + "_p99_us"] = round(res.p99_us, 1)
+            if name == "served":
+                # how the ring stage took the requests: published by their
+                # submitting thread, or through the client queues
+                q = after.ring_queued - before.ring_queued
+                row["served_queued_frac"] = round(q / max(res.completed, 1), 4)
+                row["served_max_queued"] = int(after.ring_max_queued)
+                row["served_reap_ns_per_req"] = round(
+                    (after.ring_reap_ns - before.ring_reap_ns) /
+                    max(after.completed - before.completed, 1), 1)
+                row["served_submit_call_p50_us"] = round(
+                    res.submit_call_p50_us, 2)
         sweep.append(row)
     out["rate_sweep"] = sweep
     # GB/s each form sustains in the sweep with p99 within a bound

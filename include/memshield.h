@@ -195,7 +195,13 @@ typedef struct ms_stats {
     uint64_t max_inflight_bytes;  /* high-water mark of inflight_bytes */
     uint64_t max_batch_requests;  /* largest batch formed */
     uint64_t max_inflight_batches;/* most fused launches on the device at once */
-    uint64_t reserved[4];
+    uint64_t ring_direct;         /* ring stage: requests published by their
+                                     submitting thread at once */
+    uint64_t ring_queued;         /* ring stage: requests that waited in the
+                                     client queues */
+    uint64_t ring_max_queued;     /* high-water mark of those queues */
+    uint64_t ring_reap_ns;        /* time in ring reaping passes that
+                                     finished at least one request */
 } ms_stats;
 
 /* Fill `cfg` with the defaults listed in ms_config. */

@@ -70,7 +70,10 @@ typedef struct ms_serve_result {
     uint64_t first_failed;     /* 1 + index of the first failed request,
                                   0 if none */
     int64_t first_failed_state;/* its completion state (an ms_status) */
-    uint64_t reserved[2];
+    double submit_call_p50_us; /* time inside the submitting call (ms_submit,
+                                  the resident submit, or the launch and its
+                                  event record), median and 99th percentile */
+    double submit_call_p99_us;
 } ms_serve_result;
 
 /*

@@ -49,6 +49,11 @@ constexpr uint32_t kMaxKeysLimit = 65536;
 // once); longer ones, which are bound by bandwidth rather than latency, go
 // to the fused launches.
 constexpr uint64_t kRingMaxPages = 1024;
+// The ring stage's reaper runs at most this often while nothing is short,
+// and reads the completion words of a request nobody has polled to
+// completion only this long after its publication.
+constexpr int kRingReapEveryUs = 10;
+constexpr int kRingReapWordsAfterUs = 200;
 static_assert(ms::kStaticBatchMaxRequests == MS_STATIC_BATCH_MAX_REQUESTS,
               "static batch limit");
 static_assert(ms::kCipherChaCha == MS_CIPHER_CHACHA &&
@@ -149,7 +154,16 @@ struct ClientQueues {
   }
 };
 
-struct TicketSlot {
+// A key slot's count of requests in flight, one cache line per slot:
+// submitting threads of different clients and the reaper update
+// neighbouring slots at once.
+struct alignas(64) KeyRef : std::atomic<int64_t> {
+  KeyRef() : std::atomic<int64_t>(0) {}
+};
+
+// One cache line per slot: neighbouring slots belong to different
+// submitting threads and the reaper.
+struct alignas(64) TicketSlot {
   std::atomic<uint32_t> gen{0};
   std::atomic<int32_t> state{0};  // 0 pending, 1 done, <0 ms_status
   // ring serving stage: the ring ticket once the request is published (0
@@ -163,6 +177,12 @@ struct TicketSlot {
 // that reads a matching `seq` sees the other fields.
 struct RingMeta {
   std::atomic<uint64_t> seq{0};
+  // first position + 1 once a poll has read all of the request's completion
+  // words as done, so that the reaper need not read them again (a stale
+  // poll of an earlier occupant writes its own position, which never
+  // matches a later one)
+  std::atomic<uint64_t> seen{0};
+  Clock::time_point published{};
   uint32_t ticket_slot = 0;
   uint32_t key_slot = 0;
   uint64_t n_pages = 0;
@@ -200,7 +220,7 @@ struct ms_ctx {
   uint8_t* h_staging = nullptr;     // pinned, 32 bytes
   std::vector<uint32_t> key_gen;    // current generation per slot
   std::vector<uint8_t> key_live;
-  std::unique_ptr<std::atomic<int64_t>[]> key_refs;  // submitted, unfinished
+  std::unique_ptr<KeyRef[]> key_refs;  // submitted, unfinished
 
   // ---- batched launches from ms_process_batch ----
   std::mutex batch_mu;
@@ -227,7 +247,9 @@ struct ms_ctx {
   std::vector<TicketSlot> tickets;
   std::mutex ticket_mu;
   std::vector<uint32_t> ticket_free;
-  std::atomic<uint64_t> outstanding{0};
+  // the counters below that submitting threads and the reaper both update
+  // each have a cache line of their own
+  alignas(64) std::atomic<uint64_t> outstanding{0};
 
   std::mutex q_mu;  // submission queue (multiple producers)
   std::condition_variable q_cv;
@@ -252,7 +274,7 @@ struct ms_ctx {
   std::deque<InflightBatch> inflight;
   // page bytes admitted on either stage and not yet reaped (the admission
   // cap applies to it; reserve_admission takes from it atomically)
-  std::atomic<uint64_t> inflight_bytes{0};
+  alignas(64) std::atomic<uint64_t> inflight_bytes{0};
 
   // ring serving stage (serve_stage): a resident kernel on its own HSA
   // queue reads each request's pages from a descriptor ring in mapped
@@ -263,16 +285,16 @@ struct ms_ctx {
   std::atomic<ms_resident*> ring{nullptr};
   bool ring_failed = false;                 // (sched_mu)
   // Requests are reaped in ring order: ring_reap_pos is the first position
-  // of the oldest request not yet reaped, ring_done_pos the end of the
-  // ring's completed prefix (every position below it is done; ms_poll
-  // reads it too).  Both move only forward, on the thread that holds
-  // sched_mu.
+  // of the oldest request not yet reaped, and ring_done_pos its copy for
+  // ms_poll (every position below it is done).  Both move only forward, on
+  // the thread that holds sched_mu.
   std::unique_ptr<RingMeta[]> ring_meta;    // ring_depth entries
   uint64_t ring_reap_pos = 0;               // (sched_mu)
+  Clock::time_point ring_last_reap{};       // (sched_mu)
   std::atomic<uint64_t> ring_done_pos{0};
   std::vector<RingDone> ring_batch;         // the reaper's (sched_mu)
-  std::atomic<uint64_t> ring_desc{0};       // ring positions held
-  std::atomic<uint64_t> ring_reqs{0};       // requests published, not reaped
+  alignas(64) std::atomic<uint64_t> ring_desc{0};  // ring positions held
+  alignas(64) std::atomic<uint64_t> ring_reqs{0};  // published, not reaped
   uint32_t ring_depth = 1u << 16;
   uint32_t ring_workers = 0;
 
@@ -282,10 +304,12 @@ struct ms_ctx {
   HostPath* host = nullptr;
 
   // ---- stats ----
-  std::atomic<uint64_t> st_submitted{0}, st_completed{0}, st_eagain{0},
+  alignas(64) std::atomic<uint64_t> st_completed{0};  // the reaper's
+  alignas(64) std::atomic<uint64_t> st_submitted{0}, st_eagain{0},
       st_batches{0}, st_pages{0}, st_pf_issued{0}, st_pf_dropped{0},
       st_cancelled{0}, st_max_inflight{0},
-      st_max_batch{0}, st_max_inflight_batches{0};
+      st_max_batch{0}, st_max_inflight_batches{0}, st_ring_direct{0},
+      st_ring_queued{0}, st_ring_max_queued{0}, st_ring_reap_ns{0};
 };
 
 namespace {
@@ -859,50 +883,71 @@ void publish_reserved(ms_ctx* c, ms_resident* r, const Pending& p) {
   m.ticket_slot = p.ticket_slot;
   m.key_slot = ks;
   m.n_pages = count;
+  m.published = Clock::now();
   m.seq.store(first + 1, std::memory_order_release);
   c->st_pages.fetch_add(p.req.n_pages);
   if (p.prefetch) c->st_pf_issued.fetch_add(1);
 }
 
 // Complete finished ring requests (caller holds sched_mu); true when any
-// was.  Requests are taken in ring order from the oldest: a request is
-// finished once the ring's completed prefix covers its positions, and the
-// walk stops at the first that is not (or whose publisher has not yet
-// recorded it), so a pass costs one read per newly completed position plus
-// one per request it finishes, not one per request in flight.  What the
-// finished requests hold (tickets, admission bytes, ring positions) is
-// released together, under one lock.
+// was.  Requests are taken in ring order from the oldest, and the walk stops
+// at the first that is not finished (or whose publisher has not yet
+// recorded it).  A request a poll has already seen finished costs no read of
+// host memory.  Any other is left to its client's polls for
+// kRingReapWordsAfterUs after its publication, unless ring positions,
+// tickets or admission run short; after that the reaper checks its
+// completion words itself, last position first (the unfinished head costs
+// one read).  So in the usual case, where clients poll, each completion
+// word is read by one thread only.  What the finished requests hold
+// (tickets, admission bytes, ring positions) is released together, under
+// one lock, and every position before the walk's end is then known
+// complete (the prefix ms_poll reads first).
 bool ring_reap(ms_ctx* c) {
   ms_resident* r = c->ring.load(std::memory_order_acquire);
   if (!r || c->ring_reqs.load(std::memory_order_acquire) == 0) return false;
+  // Clients see completion in the completion words, not through the
+  // reaper, so while nothing is short (no request waits for positions, the
+  // ring and the tickets are less than half used) a pass runs at most every
+  // kRingReapEveryUs: fewer, larger passes touch the counters the
+  // submitting threads update less often.
+  const auto t_start = Clock::now();
+  const bool short_ =
+      c->ring_q_n.load(std::memory_order_relaxed) != 0 ||
+      c->ring_pf_n.load(std::memory_order_relaxed) != 0 ||
+      c->ring_desc.load(std::memory_order_relaxed) >= c->ring_depth / 2 ||
+      c->outstanding.load(std::memory_order_relaxed) >= c->cfg.queue_depth / 2;
+  if (!short_ && t_start - c->ring_last_reap <
+                     std::chrono::microseconds(kRingReapEveryUs))
+    return false;
+  c->ring_last_reap = t_start;
+  const auto words_before =
+      t_start - std::chrono::microseconds(kRingReapWordsAfterUs);
   const uint64_t mask = c->ring_depth - 1;
   const uint64_t published = ms_internal_ring_published(r);
   const bool gone = !ms_internal_ring_alive(r);
-  const uint64_t done = ms_internal_ring_advance(
-      r, c->ring_done_pos.load(std::memory_order_relaxed), published);
-  c->ring_done_pos.store(done, std::memory_order_release);
   std::vector<RingDone>& batch = c->ring_batch;
   batch.clear();
   uint64_t pos = c->ring_reap_pos, pages = 0;
   while (pos < published) {
     const RingMeta& m = c->ring_meta[pos & mask];
     if (m.seq.load(std::memory_order_acquire) != pos + 1) break;
-    int32_t state = 1;
-    if (pos + m.n_pages > done) {
-      if (!gone) break;
-      // the kernel has ended: what it has not completed never will (its
-      // positions may still have completed out of order)
-      const uint64_t end = pos + m.n_pages;
-      bool all = true;
-      for (uint64_t q = pos; q < end && all; ++q)
+    const uint64_t end = pos + m.n_pages;
+    bool all = m.seen.load(std::memory_order_acquire) == pos + 1;
+    if (!all) {
+      // left to its client's polls for a while, unless something is short
+      if (!short_ && !gone && m.published > words_before) break;
+      all = ms_internal_ring_advance(r, end - 1, end) == end;
+      for (uint64_t q = pos; q + 1 < end && all; ++q)
         all = ms_internal_ring_advance(r, q, q + 1) == q + 1;
-      state = all ? 1 : MS_EDEVICE;
     }
-    batch.push_back({m.ticket_slot, m.key_slot, state});
+    // once the kernel has ended, what it has not completed never will
+    if (!all && !gone) break;
+    batch.push_back({m.ticket_slot, m.key_slot, all ? 1 : MS_EDEVICE});
     pages += m.n_pages;
-    pos += m.n_pages;
+    pos = end;
   }
   if (batch.empty()) return false;
+  c->ring_done_pos.store(pos, std::memory_order_release);
   for (const RingDone& d : batch) c->key_refs[d.key_slot].fetch_sub(1);
   {
     std::lock_guard<std::mutex> lk(c->ticket_mu);
@@ -921,6 +966,11 @@ bool ring_reap(ms_ctx* c) {
   c->inflight_bytes.fetch_sub(pages * MS_PAGE_SIZE);
   c->ring_desc.fetch_sub(pages);
   c->ring_reqs.fetch_sub(n);
+  c->st_ring_reap_ns.fetch_add(
+      (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+          Clock::now() - t_start)
+          .count(),
+      std::memory_order_relaxed);
   return true;
 }
 
@@ -1076,7 +1126,12 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
   if (!reqs) return MS_EINVAL;
   ms_status st = check_sticky(c);
   if (st) return st;
-  std::vector<uint32_t> ks(n);
+  // per-thread scratch, reused from call to call (no allocation per
+  // submission once a thread has submitted as many requests at once)
+  thread_local std::vector<uint32_t> ks, ts;
+  thread_local std::vector<ms_ticket> tk;
+  thread_local std::vector<Pending> direct, queued;
+  ks.resize(n);
   for (size_t i = 0; i < n; ++i) {
     st = check_request(c, reqs[i], &ks[i], false);
     if (st) return st;
@@ -1106,7 +1161,7 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
       return MS_OK;
     }
   }
-  std::vector<uint32_t> ts(n);
+  ts.resize(n);
   st = alloc_tickets(c, n, ts.data());
   if (st) {
     c->outstanding.fetch_sub(n);
@@ -1121,7 +1176,7 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
   }
   // the tickets are formed now: once a request is published it may finish
   // and its slot be reused (a later generation) before this call returns
-  std::vector<ms_ticket> tk(n);
+  tk.resize(n);
   for (size_t i = 0; i < n; ++i) tk[i] = make_ticket(c, ts[i]);
   // Take a reference on every key under the key lock, re-checking that each
   // handle is still live, so that ms_key_destroy cannot slip in between.
@@ -1149,7 +1204,8 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
   // the others queue for the scheduler.  Whether anything waits is read
   // from the queue sizes without the queue lock; once one of this call's
   // requests queues, the rest queue behind it.
-  std::vector<Pending> direct, queued;
+  direct.clear();
+  queued.clear();
   ms_resident* ring =
       c->ring_mode ? c->ring.load(std::memory_order_acquire) : nullptr;
   bool ring_queued = false;
@@ -1176,19 +1232,25 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
     }
     queued.push_back(p);
   }
+  uint64_t ring_waiting = 0;
   if (!queued.empty()) {
     std::lock_guard<std::mutex> lk(c->q_mu);
     for (const Pending& p : queued) {
-      if (c->ring_mode && p.req.n_pages <= kRingMaxPages && prefetch)
+      if (c->ring_mode && p.req.n_pages <= kRingMaxPages && prefetch) {
         c->ring_pf_q.push_back(p);
-      else if (c->ring_mode && p.req.n_pages <= kRingMaxPages)
+      } else if (c->ring_mode && p.req.n_pages <= kRingMaxPages) {
         c->ring_q.push(p);
-      else
+        ++ring_waiting;
+      } else
         (prefetch ? c->prefetch_q : c->demand_q).push_back(p);
     }
     c->ring_q_n.store(c->ring_q.size(), std::memory_order_relaxed);
     c->ring_pf_n.store(c->ring_pf_q.size(), std::memory_order_relaxed);
+    if (c->ring_q.size() > c->st_ring_max_queued.load(std::memory_order_relaxed))
+      c->st_ring_max_queued.store(c->ring_q.size(), std::memory_order_relaxed);
   }
+  if (ring_waiting) c->st_ring_queued.fetch_add(ring_waiting);
+  if (!direct.empty()) c->st_ring_direct.fetch_add(direct.size());
   for (const Pending& p : direct) publish_reserved(c, ring, p);
   if (!direct.empty()) {
     c->st_batches.fetch_add(1);
@@ -1410,7 +1472,7 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
     secure_zero(c->h_staging, MS_KEY_BYTES);
     c->key_gen.assign(cfg.max_keys, 0);
     c->key_live.assign(cfg.max_keys, 0);
-    c->key_refs.reset(new std::atomic<int64_t>[cfg.max_keys]);
+    c->key_refs.reset(new KeyRef[cfg.max_keys]);
     for (uint32_t i = 0; i < cfg.max_keys; ++i) c->key_refs[i].store(0);
     c->tickets = std::vector<TicketSlot>(cfg.queue_depth);
     c->ticket_free.reserve(cfg.queue_depth);
@@ -1701,9 +1763,15 @@ ms_status ms_poll(ms_ctx* c, const ms_ticket* t, size_t n, int32_t* done,
           uint64_t first = 0, count = 0;
           ms_internal_ring_span(rt, &first, &count);
           if (first + count <=
-                  c->ring_done_pos.load(std::memory_order_acquire) ||
-              ms_internal_ring_done(r, rt))
+              c->ring_done_pos.load(std::memory_order_acquire)) {
             state = 1;
+          } else if (ms_internal_ring_done(r, rt)) {
+            state = 1;
+            // spare the reaper the reads (a stale ticket writes its own
+            // position, which no later request at this slot can match)
+            c->ring_meta[first & (c->ring_depth - 1)].seen.store(
+                first + 1, std::memory_order_release);
+          }
         }
       }
       const uint32_t cur = ts.gen.load(std::memory_order_acquire);
@@ -1906,6 +1974,10 @@ ms_status ms_get_stats(ms_ctx* c, ms_stats* o) {
   o->max_inflight_bytes = c->st_max_inflight.load();
   o->max_batch_requests = c->st_max_batch.load();
   o->max_inflight_batches = c->st_max_inflight_batches.load();
+  o->ring_direct = c->st_ring_direct.load();
+  o->ring_queued = c->st_ring_queued.load();
+  o->ring_max_queued = c->st_ring_max_queued.load();
+  o->ring_reap_ns = c->st_ring_reap_ns.load();
   return MS_OK;
 }
 

@@ -133,6 +133,7 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
 
   std::vector<Clock::time_point> done_t(n);
   std::vector<double> late(n, 0.0);
+  std::vector<double> call_us(n, 0.0);  // time inside the submitting call
   std::vector<int32_t> state(n, 0);
   std::atomic<uint64_t> retries{0};
   std::atomic<int32_t> fail{0};
@@ -162,6 +163,7 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
         late[i] = us_between(arrival(i), Clock::now());
         ms_request r = make_request(tr, i, keys, src_pool, dst_pool);
         ms_ticket tk = 0;
+        const auto c0 = Clock::now();
         for (;;) {
           const ms_status s = submit_one(i, r, &tk);
           if (s == MS_OK) break;
@@ -173,6 +175,7 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
           std::this_thread::yield();
         }
         if (fail.load()) break;
+        call_us[i] = us_between(c0, Clock::now());
         std::lock_guard<std::mutex> lk(mu);
         fresh.emplace_back(i, tk);
       }
@@ -274,6 +277,7 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
       wait_until(arrival(i));
       late[i] = us_between(arrival(i), Clock::now());
       ms_request r = make_request(tr, i, keys, src_pool, dst_pool);
+      const auto c0 = Clock::now();
       ms_status ps =
           (r.op == MS_DECRYPT)
               ? ms_decrypt_pages(c, r.key, r.src, r.dst, r.n_pages, &r.nonce, s)
@@ -282,6 +286,7 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
         fail.store(ps != MS_OK ? ps : MS_EDEVICE);
         break;
       }
+      call_us[i] = us_between(c0, Clock::now());
       issued.store(i + 1, std::memory_order_release);
     }
     poller.join();
@@ -325,5 +330,8 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
   res->max_us = srt.back();
   res->completed = n;
   res->eagain_retries = retries.load();
+  std::sort(call_us.begin(), call_us.end());
+  res->submit_call_p50_us = percentile(call_us, 0.50);
+  res->submit_call_p99_us = percentile(call_us, 0.99);
   return MS_OK;
 }

@@ -110,8 +110,8 @@ class ms_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "submitted", "completed", "rejected_eagain", "batches", "pages",
         "prefetch_issued", "prefetch_dropped", "cancelled", "inflight_bytes",
-        "max_inflight_bytes", "max_batch_requests", "max_inflight_batches")] + \
-        [("reserved", ctypes.c_uint64 * 4)]
+        "max_inflight_bytes", "max_batch_requests", "max_inflight_batches",
+        "ring_direct", "ring_queued", "ring_max_queued", "ring_reap_ns")]
 
 
 MS_SERVE_BATCHED = 0
@@ -134,7 +134,8 @@ class ms_serve_result(ctypes.Structure):
         [(n, ctypes.c_uint64) for n in ("completed", "eagain_retries",
                                         "failed", "first_failed")] + \
         [("first_failed_state", ctypes.c_int64),
-         ("reserved", ctypes.c_uint64 * 2)]
+         ("submit_call_p50_us", ctypes.c_double),
+         ("submit_call_p99_us", ctypes.c_double)]
 
 
 class ms_launch_info(ctypes.Structure):

@@ -101,7 +101,9 @@ def summarize(res) -> dict:
             "requests": int(res.completed), "wall_s": round(res.wall_s, 3),
             "eagain_retries": int(res.eagain_retries),
             "failed": int(res.failed),
-            "late_submit_us_max": round(res.late_submit_us_max, 1)}
+            "late_submit_us_max": round(res.late_submit_us_max, 1),
+            "submit_call_p50_us": round(res.submit_call_p50_us, 2),
+            "submit_call_p99_us": round(res.submit_call_p99_us, 2)}
 
 
 def sampled_outputs(lay: Layout, src: torch.Tensor, dst: torch.Tensor):
