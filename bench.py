@@ -961,6 +961,8 @@ def main():
                     help="skip both host-memory page paths (host_resident "
                          "and resident_key)")
     ap.add_argument("--no-resident", action="store_true")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving section and print its line")
     ap.add_argument("--resident-device-only", action="store_true",
                     help="run only the resident-key engine on 1 GiB of HBM "
                          "pages (for profiling) and print its line")
@@ -991,6 +993,10 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     ms.load_library()
+    if args.serving_only:
+        print(json.dumps({"serving": run_serving(args, ms, torch)}),
+              flush=True)
+        return
     if args.predictor_only:
         print(json.dumps({"predictor": run_predictor(args, ms, torch)}),
               flush=True)
