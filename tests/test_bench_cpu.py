@@ -71,3 +71,45 @@ def test_traffic_calibration_arithmetic(tmp_path):
     assert float(vals["fetch_bytes_per_launch"]) == pytest.approx(1.5 * 2**30)
     assert float(vals["write_bytes_per_launch"]) == pytest.approx(2**30)
     assert float(vals["traffic_over_algorithmic"]) == pytest.approx(1.25)
+
+
+def test_resident_summary_arithmetic(tmp_path):
+    """profsum's resident summary: bytes per page from FETCH_SIZE and
+    WRITE_SIZE calibrated on the copy probe of the same run, instructions
+    per page, the waiting share of wave cycles."""
+    from paper_2004_09252_amd import profsum
+    k = "ms_resident_pages_r20"
+    c = "ms::(anonymous namespace)::copy_probe_kernel(a, b, c)"
+    pages = 1000
+    # FETCH_SIZE reads half of the bytes (the copy's 1 GiB reads 512 MiB)
+    _db(tmp_path / "f.db", [(k, "FETCH_SIZE", pages * 4096 / 1024 / 2, 1.0),
+                            (c, "FETCH_SIZE", 524288.0, 1.0)])
+    _db(tmp_path / "w.db", [(k, "WRITE_SIZE", pages * 4096 / 1024, 1.0),
+                            (c, "WRITE_SIZE", 1048576.0, 1.0)])
+    _db(tmp_path / "s.db", [(k, "SQ_INSTS_VALU", 976.5 * pages, 1.0),
+                            (k, "SQ_WAVES", 1024.0, 1.0),
+                            (k, "SQ_BUSY_CYCLES", 10.0, 1.0),
+                            (k, "SQ_WAIT_ANY", 1.0, 1.0),
+                            (k, "SQ_WAVE_CYCLES", 4.0, 1.0),
+                            (k, "GRBM_GUI_ACTIVE", 800.0, 1.0)])
+    db = sqlite3.connect(tmp_path / "t.db")
+    db.execute("create table kernels (name text, duration real, "
+               "vgpr_count int, sgpr_count int, lds_size int, grid_x int, "
+               "workgroup_x int)")
+    db.execute("insert into kernels values (?, ?, ?, ?, ?, ?, ?)",
+               (k, 2.5e6, 64, 96, 18432, 65536, 256))
+    db.commit()
+    db.close()
+    out = tmp_path / "r.txt"
+    profsum.resident(str(tmp_path / "t.db"), str(tmp_path / "f.db"),
+                     str(tmp_path / "w.db"), str(tmp_path / "s.db"), pages,
+                     str(out), "cmd")
+    vals = dict(l.split(": ", 1) for l in out.read_text().splitlines()
+                if ": " in l and not l.startswith("#"))
+    assert float(vals["hbm_fetch_bytes_per_page"]) == pytest.approx(4096)
+    assert float(vals["hbm_write_bytes_per_page"]) == pytest.approx(4096)
+    assert float(vals["valu_instructions_per_page"]) == pytest.approx(976.5)
+    assert float(vals["wave_cycles_waiting_frac"]) == pytest.approx(0.25)
+    assert float(vals["dispatch_duration_ms"]) == pytest.approx(2.5)
+    assert vals["workgroups_x_threads"] == "256 x 256"
+    assert float(vals["grbm_gui_active_cycles_per_xcd"]) == pytest.approx(100)
