@@ -65,9 +65,11 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def read_traffic():
+def read_traffic(kernel=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel source changed since the counters were taken."""
+    None when the kernel source changed since the counters were taken, or
+    when `kernel` (the launched kernel's name) is not the one they were
+    taken on."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -76,6 +78,8 @@ def read_traffic():
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    if kernel is not None and vals.get("kernel") != kernel:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -1033,7 +1037,7 @@ def main():
     med_launch_s = (srt[(len(srt) - 1) // 2] + srt[len(srt) // 2]) / 2e3
     ops = float(OPS_PER_PAGE) * n
     achieved_ops = ops / avg_launch_s
-    traffic = read_traffic()
+    traffic = read_traffic(launch["kernel"])
     line = {
         "metric": METRIC,
         "value": round(value, 3),

@@ -211,7 +211,7 @@ struct ms_ctx {
   hipStream_t stream = nullptr;
   int cu_count = 0;
   std::string arch;
-  uint32_t resident_plain_wpc = 0;     // resident waves/CU, plain unroll-2
+  uint32_t resident_plain_wpc[3] = {0, 0, 0};  // resident waves/CU, by unroll
   uint32_t resident_batch_wpc[3] = {0, 0, 0};  // by unroll
 
   // ---- key store ----
@@ -453,13 +453,20 @@ Tuning tuning_for(ms_ctx* c, uint64_t n_pages) {
   return default_tuning(n_pages);
 }
 
-// Plain launches: persistent waves, as many as fit on the chip at once, the
-// next page's loads overlapped with the current page's cipher work.
-Tuning plain_tuning(ms_ctx* c) {
+// Plain launches: persistent waves, as many as fit on the chip at once.  At
+// full residency the unroll-1 kernel (51-56 VGPRs, 8 waves per SIMD) hides
+// memory latency across its waves and measured ~1% faster than the
+// unroll-2 kernel (65-71 VGPRs, 7 waves per SIMD), whose waves keep their
+// next page's loads in flight during the current page's rounds; 8 waves
+// per SIMD also split 2^18 pages evenly (32 per wave).  A launch capped to
+// few waves (pages in host memory, bound by the link) keeps unroll 2, where
+// each wave's own overlap is what hides the latency.
+Tuning plain_tuning(ms_ctx* c, bool capped) {
   Tuning t;
   t.ppw = 1;
-  t.unroll = 2;
-  t.waves_per_cu = c->resident_plain_wpc ? c->resident_plain_wpc : 28;
+  t.unroll = capped ? 2 : 1;
+  const uint32_t wpc = c->resident_plain_wpc[t.unroll];
+  t.waves_per_cu = wpc ? wpc : 28;
   return t;
 }
 
@@ -809,7 +816,7 @@ bool launch_one(ms_ctx* c) {
     a.n_pages = r.n_pages;
     a.key_slot = ks[0];
     a.nonce_tag = r.nonce.tag;
-    const Tuning t = plain_tuning(c);
+    const Tuning t = plain_tuning(c, false);
     hipError_t e = ms::launch_plain(
         a, r.nonce.kind == MS_NONCE_ARRAY ? ms::kNonceArray : ms::kNonceLinear,
         c->cfg.cipher, (int)c->cfg.rounds,
@@ -1284,8 +1291,9 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
   return MS_OK;
 }
 
-// One run of pages with one key: the plain kernel, unroll 2, as many waves
-// as stay resident.
+// One run of pages with one key: the plain kernel with as many waves as stay
+// resident (unroll 1), or at most max_waves waves when that is fewer
+// (unroll 2).
 ms_status launch_plain_run(ms_ctx* c, uint32_t slot, const void* src,
                            void* dst, uint64_t n_pages, const ms_nonce& nonce,
                            hipStream_t s, uint32_t max_waves = 0) {
@@ -1302,14 +1310,14 @@ ms_status launch_plain_run(ms_ctx* c, uint32_t slot, const void* src,
   a.nonce_tag = nonce.tag;
   const uint32_t kind =
       nonce.kind == MS_NONCE_ARRAY ? ms::kNonceArray : ms::kNonceLinear;
-  const Tuning t = plain_tuning(c);
-  const uint32_t resident = (uint32_t)c->cu_count * t.waves_per_cu;
+  const Tuning full = plain_tuning(c, false);
+  const uint32_t resident = (uint32_t)c->cu_count * full.waves_per_cu;
+  const bool capped = max_waves && max_waves < resident;
+  const Tuning t = capped ? plain_tuning(c, true) : full;
   return dev_err(c, ms::launch_plain(a, kind, c->cfg.cipher,
                                      (int)c->cfg.rounds,
-                                     max_waves && max_waves < resident
-                                         ? max_waves
-                                         : resident,
-                                     t.unroll, s));
+                                     capped ? max_waves : resident, t.unroll,
+                                     s));
 }
 
 ms_status plain_call(ms_ctx* c, ms_key key, const void* src, void* dst,
@@ -1451,8 +1459,9 @@ ms_status ms_init(ms_ctx** out, int hip_device, const ms_config* cfg_in) {
       return MS_ENOMEM;
     }
   }
-  c->resident_plain_wpc = ms::resident_waves_per_cu(
-      ms::plain_kernel_fn(2, cfg.cipher, (int)cfg.rounds, ms::kNonceLinear));
+  for (uint32_t u = 1; u <= 2; ++u)
+    c->resident_plain_wpc[u] = ms::resident_waves_per_cu(
+        ms::plain_kernel_fn(u, cfg.cipher, (int)cfg.rounds, ms::kNonceLinear));
   for (uint32_t u = 1; u <= 2; ++u)
     c->resident_batch_wpc[u] =
         ms::resident_waves_per_cu(
@@ -1623,7 +1632,7 @@ ms_status ms_plain_launch_info(ms_ctx* c, uint64_t n_pages,
   if (nonce_kind != MS_NONCE_ARRAY && nonce_kind != MS_NONCE_LINEAR)
     return MS_EINVAL;
   // the arithmetic of launch_plain_run and ms::launch_plain
-  const Tuning t = plain_tuning(c);
+  const Tuning t = plain_tuning(c, false);
   const uint64_t max_waves = (uint64_t)c->cu_count * t.waves_per_cu;
   const uint64_t first =
       n_pages < ms::kMaxPagesPerPlainLaunch ? n_pages

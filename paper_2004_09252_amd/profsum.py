@@ -45,8 +45,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = [os.path.join(HERE, "csrc", f)
                   for f in ("page_cipher.hip", "cipher_core.h")]
 COPY_BYTES = 1 << 30
-# ChaCha (cipher 0), 20 rounds, unroll 2, linear nonces
-BULK_KERNEL = "plain_pages_kernel<0u, 20, 2, 1u>"
+# ChaCha (cipher 0), 20 rounds, unroll 1, linear nonces
+BULK_KERNEL = "plain_pages_kernel<0u, 20, 1, 1u>"
 COPY_KERNEL = "copy_probe_kernel"
 PROBE_KERNEL = "valu_probe_kernel"
 N_XCD = 8   # GRBM_GUI_ACTIVE comes summed over the 8 XCDs of an MI355X

@@ -36,8 +36,10 @@ def test_committed_traffic_summary_matches_kernel_sources():
     """bench.py reports roofline.traffic only while the counters in
     profiles/ were taken on the current kernel sources."""
     import bench
-    t = bench.read_traffic()
-    assert t is not None, "kernel sources changed since the counters"
+    from paper_2004_09252_amd import profsum
+    t = bench.read_traffic(profsum.BULK_KERNEL)
+    assert t is not None, ("kernel sources or the bulk kernel changed since "
+                           "the counters")
     assert abs(t / (2 * 262144 * 4096) - 1) < 0.01
 
 

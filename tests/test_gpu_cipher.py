@@ -381,19 +381,19 @@ def test_plain_launch_info_names_the_launch(ms, eng):
     waves (or one wave per page below that)."""
     st, i = ms.ms_plain_launch_info(eng.ctx, 262144, ms.MS_NONCE_LINEAR)
     assert st == 0
-    assert i.kernel.decode() == "plain_pages_kernel<0u, 20, 2, 1u>"
-    assert i.launches == 1 and i.block_threads == 256
+    assert i.kernel.decode() == "plain_pages_kernel<0u, 20, 1, 1u>"
+    assert i.launches == 1 and i.block_threads == 256 and i.unroll == 1
     cus = ms.ms_device_cu_count(eng.ctx)
     assert i.grid_blocks == cus * i.waves_per_cu // 4
     st, i = ms.ms_plain_launch_info(eng.ctx, (1 << 24) + 3, ms.MS_NONCE_ARRAY)
     assert st == 0 and i.launches == 2
-    assert i.kernel.decode() == "plain_pages_kernel<0u, 20, 2, 0u>"
+    assert i.kernel.decode() == "plain_pages_kernel<0u, 20, 1, 0u>"
     st, i = ms.ms_plain_launch_info(eng.ctx, 10, ms.MS_NONCE_LINEAR)
     assert st == 0 and i.grid_blocks == 3
     e = ms.Engine(0, cipher=ms.MS_CIPHER_SALSA, rounds=12)
     try:
         st, i = ms.ms_plain_launch_info(e.ctx, 5, ms.MS_NONCE_LINEAR)
-        assert i.kernel.decode() == "plain_pages_kernel<1u, 12, 2, 1u>"
+        assert i.kernel.decode() == "plain_pages_kernel<1u, 12, 1, 1u>"
     finally:
         e.close()
     assert ms.ms_plain_launch_info(eng.ctx, 0, 1)[0] == ms.MS_EINVAL
