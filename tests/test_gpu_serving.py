@@ -446,6 +446,12 @@ def test_ring_stage_serves_clients_round_robin(ms):
                                     src_offset_pages=i, dst_offset_pages=i)
                          for i in range(nb)])
         tickets = list(ta) + list(tb)
+        stats = eng.stats()
+        # the first ring's worth of the burst went straight onto the ring,
+        # the rest of it and all of B's requests waited in client queues
+        assert stats.ring_direct >= 60, stats.ring_direct
+        assert stats.ring_queued >= na - 64 + nb, stats.ring_queued
+        assert stats.ring_max_queued >= na - 64, stats.ring_max_queued
         seen = [None] * len(tickets)
         it = 0
         deadline = time.time() + 60
