@@ -461,19 +461,33 @@ Tuning tuning_for(ms_ctx* c, uint64_t n_pages) {
 // per SIMD also split 2^18 pages evenly (32 per wave).  A launch capped to
 // few waves (pages in host memory, bound by the link) keeps unroll 2, where
 // each wave's own overlap is what hides the latency.
+// Wave slots per compute unit that resident kernels running on the device
+// hold (one wave per SIMD each): a grid sized for an idle device would
+// leave its last workgroups to start only after the first ones finish.
+uint32_t resident_busy_wpc(ms_ctx* c) {
+  return ms::kWavesPerBlock * ms_internal_resident_live(c->device);
+}
+
 Tuning plain_tuning(ms_ctx* c, bool capped) {
   Tuning t;
   t.ppw = 1;
   t.unroll = capped ? 2 : 1;
-  const uint32_t wpc = c->resident_plain_wpc[t.unroll];
-  t.waves_per_cu = wpc ? wpc : 28;
+  uint32_t wpc = c->resident_plain_wpc[t.unroll];
+  if (!wpc) wpc = 28;
+  const uint32_t busy = resident_busy_wpc(c);
+  t.waves_per_cu = wpc > busy + ms::kWavesPerBlock ? wpc - busy
+                                                   : ms::kWavesPerBlock;
   return t;
 }
 
 uint32_t grid_blocks_for(ms_ctx* c, const Tuning& t, uint64_t total_pages) {
   const uint64_t items = (total_pages + t.ppw - 1) / t.ppw;
   uint32_t wpc = t.waves_per_cu;
-  const uint32_t res = c->resident_batch_wpc[t.unroll == 2 ? 2 : 1];
+  uint32_t res = c->resident_batch_wpc[t.unroll == 2 ? 2 : 1];
+  // resident kernels on the device hold some of the slots
+  const uint32_t busy = resident_busy_wpc(c);
+  if (res) res = res > busy + ms::kWavesPerBlock ? res - busy
+                                                 : ms::kWavesPerBlock;
   if (res && wpc > res) wpc = res;  // waves beyond residency start late
   const uint64_t max_waves = (uint64_t)c->cu_count * wpc;
   uint64_t waves = std::min<uint64_t>(std::max<uint64_t>(items, 1), max_waves);

@@ -91,4 +91,8 @@ uint64_t ms_internal_ring_published(ms_resident* r);
 uint64_t ms_internal_ring_advance(ms_resident* r, uint64_t from,
                                   uint64_t limit);
 bool ms_internal_ring_alive(ms_resident* r);
+// Resident kernels of this process running on `device` (any context's
+// engines and serving rings); each holds one wave on every SIMD of the
+// compute units it spans.
+uint32_t ms_internal_resident_live(int device);
 void ms_internal_ring_stop(ms_resident* r);

@@ -29,6 +29,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -83,6 +84,11 @@ constexpr uint64_t kTicketCountBits = 24;
 
 std::mutex g_reg_mu;
 std::multimap<ms_ctx*, ms_resident*> g_engines;
+// Every engine whose kernel was dispatched and not yet released, registered
+// or not (a context's serving ring is not): what ms_internal_resident_live
+// counts.
+std::mutex g_live_mu;
+std::set<ms_resident*> g_live;
 
 bool hip_ok(hipError_t e) { return e == hipSuccess; }
 
@@ -112,6 +118,10 @@ bool wait_kernel(ms_resident* r, uint64_t ms) {
 // Stop the kernel, wait for it, free everything; false if the kernel did not
 // end (its buffers are then kept).
 bool release(ms_resident* r) {
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.erase(r);
+  }
   bool drained = true;
   if (r->launched) {
     store_rel(&r->hctl->stop, 1u);
@@ -292,6 +302,10 @@ ms_status dispatch(ms_resident* r, const ms::RkArgs& args, uint32_t cipher,
                    __ATOMIC_RELEASE);
   hsa_signal_store_screlease(r->queue->doorbell_signal, (hsa_signal_value_t)index);
   r->launched = true;
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.insert(r);
+  }
   return MS_OK;
 }
 
@@ -571,6 +585,14 @@ uint64_t ms_internal_ring_advance(ms_resident* r, uint64_t from,
   while (from < limit && load_acq(&r->completed[from & (depth - 1)]) >= from + 1)
     ++from;
   return from;
+}
+
+uint32_t ms_internal_resident_live(int device) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  uint32_t n = 0;
+  for (ms_resident* r : g_live)
+    if (r->device == device && !kernel_exited(r)) ++n;
+  return n;
 }
 
 bool ms_internal_ring_alive(ms_resident* r) {

@@ -149,6 +149,9 @@ int main() {
       if (ms_key_load(c, key_a, &ka) != MS_OK) { failures++; return; }
       handle_a.store(ka);
       cycles++;
+      // give the caller a turn with the fresh handle (on a loaded machine a
+      // rotator that never yields can keep every handle it reads stale)
+      std::this_thread::yield();
     }
   };
 

@@ -199,6 +199,7 @@ __attribute__((weak)) uint64_t ms_internal_ring_advance(ms_resident*,
                                                         uint64_t) {
   return from;
 }
+__attribute__((weak)) uint32_t ms_internal_resident_live(int) { return 0; }
 __attribute__((weak)) bool ms_internal_ring_alive(ms_resident*) {
   return false;
 }

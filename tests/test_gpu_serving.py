@@ -484,6 +484,66 @@ def test_ring_stage_serves_clients_round_robin(ms):
         eng.close()
 
 
+def test_plain_launches_leave_room_for_the_ring(ms):
+    """Once a context's serving ring runs (one wave on every SIMD), plain
+    launches size their grid to the wave slots left: ms_plain_launch_info
+    reports 4 fewer waves per compute unit, a 1 GiB pass takes at most 1.35x
+    its time on an idle device (a grid sized for an idle device would leave
+    an eighth of its workgroups to start after the rest, about 2x), and its
+    output equals the oracle on sampled pages."""
+    _note("plain launch beside the serving ring")
+    import torch
+    eng = ms.Engine(0, serve_stage=ms.MS_SERVE_STAGE_RING)
+    try:
+        rng = np.random.default_rng(51)
+        kb = rng.bytes(32)
+        key = eng.key_load(kb)
+        n = 262144
+        src = torch.randint(0, 256, (n * 4096,), dtype=torch.uint8,
+                            device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        nonce = ms.linear_nonce(0, 1, 0)
+        s = torch.cuda.Stream()
+
+        def best():
+            ts = []
+            for _ in range(10):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                eng.encrypt_pages(key, src, dst, nonce, stream=s)
+                e1.record(s)
+                s.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            return min(ts[3:])
+
+        st, idle = ms.ms_plain_launch_info(eng.ctx, n, ms.MS_NONCE_LINEAR)
+        assert st == 0
+        t_idle = best()
+        one = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t = eng.submit([ms.request(key, one, one, 1, nonce)])
+        assert eng.poll(t, timeout_s=30)[0] == 0   # the ring is up
+        st, busy = ms.ms_plain_launch_info(eng.ctx, n, ms.MS_NONCE_LINEAR)
+        assert st == 0 and busy.waves_per_cu == idle.waves_per_cu - 4
+        assert busy.grid_blocks == idle.grid_blocks - eng_cus(ms, eng)
+        t_ring = best()
+        assert t_ring < 1.35 * t_idle, (t_ring, t_idle)
+        for p in (0, 1, n // 3, n - 1):
+            got = dst[p * 4096:(p + 1) * 4096].cpu().numpy().reshape(1, 4096)
+            inp = src[p * 4096:(p + 1) * 4096].cpu().numpy().reshape(1, 4096)
+            want = oracle.cipher_pages(kb, oracle.nonces_linear(1, p, 1, 0),
+                                       inp)
+            assert np.array_equal(got, want), p
+    finally:
+        eng.close()
+
+
+def eng_cus(ms, eng):
+    return ms.ms_device_cu_count(eng.ctx)
+
+
 @STAGES
 @pytest.mark.parametrize("rounds", [20, 8])
 def test_salsa20_context_serves_on_both_stages(ms, stage, rounds):
