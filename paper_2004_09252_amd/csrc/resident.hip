@@ -132,14 +132,16 @@ __device__ void poll_host(const RkArgs& a, uint32_t lane) {
 }
 
 // Cipher n_pages consecutive pages from `src` to `dst` (GPU-visible
-// addresses) with key `kk`.  ARRAY: page p's nonce is the 12 bytes at nb +
+// addresses) with the key whose words are `kv` (the same in every lane, not
+// yet made wave-uniform).  ARRAY: page p's nonce is the 12 bytes at nb +
 // 12p (every lane reads them); otherwise it is LE64(nb + p*ns) || tag.
 template <uint32_t CIPHER, int ROUNDS, bool ARRAY>
-__device__ __forceinline__ void cipher_run(const uint32_t (&kk)[8],
+__device__ __forceinline__ void cipher_run(const uint32_t (&kv)[8],
                                            uint64_t src, uint64_t dst,
                                            uint64_t nb, uint64_t ns,
                                            uint32_t tag, uint32_t n_pages,
                                            uint4* lds, uint32_t lane) {
+  uint32_t kk[8];  // the key in SGPRs, filled below
   // the page's 512 8-byte units: access q of lane l is unit 64*q + l
   auto load = [&](uint64_t (&v)[8], uint32_t p) {
     const uint64_t s = src + (uint64_t)p * kPageBytes;
@@ -184,6 +186,15 @@ __device__ __forceinline__ void cipher_run(const uint32_t (&kk)[8],
   // count is wave-uniform, so these branches are scalar.
   uint64_t va[8], vb[8];
   load(va, 0);
+  // The key words become wave-uniform only now: waiting for them here lets
+  // their load (for the serving ring, a system-scope read of the key table)
+  // overlap the first page's loads instead of preceding them.  The asm
+  // keeps each word in an SGPR, opaque to the compiler.
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    kk[i] = uni(kv[i]);
+    asm volatile("" : "+s"(kk[i]) : : "memory");
+  }
   for (uint32_t p = 0;; p += 2) {
     const bool more_b = p + 1 < n_pages;
     if (more_b) load(vb, p + 1);
@@ -235,27 +246,27 @@ __device__ void serve_one(const RkArgs& a, const uint32_t (&k)[8],
       key >= key_limit || kind > 1) {
     st_sys32(&a.hctl->error, 1u);
   } else {
-    uint32_t kk[8];
+    // the key's words (cipher_run makes them uniform once the first
+    // page's loads are issued)
+    uint32_t kv[8];
     if (a.n_keys == 0) {
       // a row of the context's key table, fresh for every descriptor
 #pragma unroll
       for (int i = 0; i < 8; ++i)
-        kk[i] = uni(ld_sys32(a.key_table + (uint64_t)key * 8u + i));
+        kv[i] = ld_sys32(a.key_table + (uint64_t)key * 8u + i);
     } else if (a.n_keys > 1) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) kk[i] = uni(keytab[key * 8u + i]);
+      for (int i = 0; i < 8; ++i) kv[i] = keytab[key * 8u + i];
     } else {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) kk[i] = k[i];
+      for (int i = 0; i < 8; ++i) kv[i] = k[i];
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) asm volatile("" : "+s"(kk[i]) : : "memory");
     // the nonce kind is decided once per descriptor, outside the page loop
     if (kind == 0)
-      cipher_run<CIPHER, ROUNDS, true>(kk, src, dst, nb, ns, tag, n_pages,
+      cipher_run<CIPHER, ROUNDS, true>(kv, src, dst, nb, ns, tag, n_pages,
                                        lds, lane);
     else
-      cipher_run<CIPHER, ROUNDS, false>(kk, src, dst, nb, ns, tag, n_pages,
+      cipher_run<CIPHER, ROUNDS, false>(kv, src, dst, nb, ns, tag, n_pages,
                                         lds, lane);
   }
   // The page stores are complete before the completion word is written.

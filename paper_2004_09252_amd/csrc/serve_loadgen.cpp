@@ -190,13 +190,18 @@ extern "C" ms_status ms_serve_run(ms_ctx* c, const ms_serve_trace* tr,
     uint64_t observed = 0;
     Clock::time_point last_arrival = arrival(n - 1);
     while (observed < n && !fail.load()) {
+      // read before taking the fresh tickets: a submitter pushes its last
+      // ticket before it counts itself done, so once all are counted here
+      // the merge below holds every ticket (read after the merge, a ticket
+      // pushed in between would be lost)
+      const bool all_submitted = submitters_done.load() == submit_threads;
       {
         std::lock_guard<std::mutex> lk(mu);
         pend.insert(pend.end(), fresh.begin(), fresh.end());
         fresh.clear();
       }
       if (pend.empty()) {
-        if (submitters_done.load() == submit_threads) break;
+        if (all_submitted) break;
         std::this_thread::yield();
         continue;
       }
