@@ -675,11 +675,14 @@ def run_serving(args, ms, torch):
         res, lat = serving.run(e, lay, ks, src, dst, mode)
         r = serving.summarize(res)
         after = e.stats()
-        if mode == ms.MS_SERVE_BATCHED:
+        if mode == ms.MS_SERVE_BATCHED and name == "served_launch_stage":
             nb = after.batches - before.batches
             r["batches"] = int(nb)
             r["requests_per_batch"] = round(res.completed / max(nb, 1), 2)
             r["max_inflight_batches"] = int(after.max_inflight_batches)
+        elif mode == ms.MS_SERVE_BATCHED:
+            r["ring_direct"] = int(after.ring_direct - before.ring_direct)
+            r["ring_queued"] = int(after.ring_queued - before.ring_queued)
         a = lay.arrays
         for i, inp, o in serving.sampled_outputs(lay, src, dst):
             c = int(a["client"][i])

@@ -186,8 +186,10 @@ typedef struct ms_stats {
     uint64_t submitted;           /* requests accepted by ms_submit */
     uint64_t completed;           /* requests finished on the device */
     uint64_t rejected_eagain;     /* submissions refused with MS_EAGAIN */
-    uint64_t batches;             /* fused launches issued by the scheduler */
-    uint64_t pages;               /* pages ciphered by the scheduler */
+    uint64_t batches;             /* fused launches issued on the launch
+                                     stage (the ring stage forms none) */
+    uint64_t pages;               /* pages of the requests served, either
+                                     stage */
     uint64_t prefetch_issued;     /* prefetch hints executed */
     uint64_t prefetch_dropped;    /* prefetch hints dropped */
     uint64_t cancelled;           /* requests cancelled before launch */

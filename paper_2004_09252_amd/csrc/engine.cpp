@@ -154,6 +154,33 @@ struct ClientQueues {
   }
 };
 
+// A statistics counter that many submitting threads bump at once: one
+// cache line per shard, each thread on a shard of its own (threads beyond
+// the shard count share), summed when read.
+class ShardedCounter {
+ public:
+  void add(uint64_t v) {
+    shard_[shard_index()].v.fetch_add(v, std::memory_order_relaxed);
+  }
+  uint64_t load() const {
+    uint64_t s = 0;
+    for (const Shard& x : shard_) s += x.v.load(std::memory_order_relaxed);
+    return s;
+  }
+
+ private:
+  static constexpr unsigned kShards = 16;
+  struct alignas(64) Shard {
+    std::atomic<uint64_t> v{0};
+  };
+  static unsigned shard_index() {
+    static std::atomic<unsigned> next{0};
+    thread_local const unsigned mine = next.fetch_add(1) % kShards;
+    return mine;
+  }
+  Shard shard_[kShards];
+};
+
 // A key slot's count of requests in flight, one cache line per slot:
 // submitting threads of different clients and the reaper update
 // neighbouring slots at once.
@@ -305,10 +332,12 @@ struct ms_ctx {
 
   // ---- stats ----
   alignas(64) std::atomic<uint64_t> st_completed{0};  // the reaper's
-  alignas(64) std::atomic<uint64_t> st_submitted{0}, st_eagain{0},
-      st_batches{0}, st_pages{0}, st_pf_issued{0}, st_pf_dropped{0},
+  // bumped by every submission: sharded
+  ShardedCounter st_submitted, st_pages, st_ring_direct;
+  alignas(64) std::atomic<uint64_t> st_eagain{0},
+      st_batches{0}, st_pf_issued{0}, st_pf_dropped{0},
       st_cancelled{0}, st_max_inflight{0},
-      st_max_batch{0}, st_max_inflight_batches{0}, st_ring_direct{0},
+      st_max_batch{0}, st_max_inflight_batches{0},
       st_ring_queued{0}, st_ring_max_queued{0}, st_ring_reap_ns{0};
 };
 
@@ -406,9 +435,11 @@ ms_status check_nonce(ms_ctx* c, const ms_nonce* n, uint64_t n_pages) {
   return MS_EINVAL;
 }
 
-// Validate one request (pages, pointers, overlap, key, nonce).
+// Validate one request (pages, pointers, overlap, key, nonce).  With
+// `resolve` false the key handle is only decoded into its slot: the caller
+// checks it under the key lock itself.
 ms_status check_request(ms_ctx* c, const ms_request& r, uint32_t* slot,
-                        bool allow_empty) {
+                        bool allow_empty, bool resolve = true) {
   if (r.priority != 0 || r.flags != 0) return MS_EINVAL;
   if (r.op != MS_ENCRYPT && r.op != MS_DECRYPT) return MS_EINVAL;
   if (r.n_pages == 0) {
@@ -426,6 +457,12 @@ ms_status check_request(ms_ctx* c, const ms_request& r, uint32_t* slot,
     if (s != d && ranges_overlap(s, bytes, d, bytes)) return MS_EINVAL;
     st = check_nonce(c, &r.nonce, r.n_pages);
     if (st) return st;
+  }
+  if (!resolve) {
+    const uint32_t ks = (uint32_t)(r.key & 0xffffffffu);
+    if (ks == 0 || ks > c->cfg.max_keys) return MS_ENOKEY;
+    *slot = ks - 1;
+    return MS_OK;
   }
   if (!resolve_key(c, r.key, slot)) return MS_ENOKEY;
   return MS_OK;
@@ -811,7 +848,7 @@ bool launch_one(ms_ctx* c) {
   const size_t copy = fill_slot(s, rp.data(), ks.data(), take.size(), &total);
   if (take.size() > c->st_max_batch.load()) c->st_max_batch.store(take.size());
   c->st_batches.fetch_add(1);
-  c->st_pages.fetch_add(total);
+  c->st_pages.add(total);
   c->st_pf_issued.fetch_add(n_pf);
   ms_status st = MS_OK;
   hipStream_t strm = c->serve_streams[stream_i];
@@ -906,7 +943,7 @@ void publish_reserved(ms_ctx* c, ms_resident* r, const Pending& p) {
   m.n_pages = count;
   m.published = Clock::now();
   m.seq.store(first + 1, std::memory_order_release);
-  c->st_pages.fetch_add(p.req.n_pages);
+  c->st_pages.add(p.req.n_pages);
   if (p.prefetch) c->st_pf_issued.fetch_add(1);
 }
 
@@ -1054,10 +1091,7 @@ bool ring_publish(ms_ctx* c) {
     ++published;
     any = true;
   }
-  if (published) {
-    if (published > c->st_max_batch.load()) c->st_max_batch.store(published);
-    c->st_batches.fetch_add(1);
-  }
+  (void)published;
   return any;
 }
 
@@ -1154,7 +1188,8 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
   thread_local std::vector<Pending> direct, queued;
   ks.resize(n);
   for (size_t i = 0; i < n; ++i) {
-    st = check_request(c, reqs[i], &ks[i], false);
+    // the handle's liveness is checked below, with the reference taken
+    st = check_request(c, reqs[i], &ks[i], false, false);
     if (st) return st;
     if (reqs[i].n_pages * MS_PAGE_SIZE > c->cfg.admission_cap_bytes)
       return MS_EINVAL;
@@ -1271,13 +1306,8 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
       c->st_ring_max_queued.store(c->ring_q.size(), std::memory_order_relaxed);
   }
   if (ring_waiting) c->st_ring_queued.fetch_add(ring_waiting);
-  if (!direct.empty()) c->st_ring_direct.fetch_add(direct.size());
+  if (!direct.empty()) c->st_ring_direct.add(direct.size());
   for (const Pending& p : direct) publish_reserved(c, ring, p);
-  if (!direct.empty()) {
-    c->st_batches.fetch_add(1);
-    if (direct.size() > c->st_max_batch.load())
-      c->st_max_batch.store(direct.size());
-  }
   if (!prefetch) {
     // direct launch on an idle device: if no batch is in flight and the
     // scheduler is not busy, form and launch the batch on this thread,
@@ -1299,7 +1329,7 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
     }
   }
   c->q_cv.notify_one();
-  if (!prefetch) c->st_submitted.fetch_add(n);
+  if (!prefetch) c->st_submitted.add(n);
   if (tickets_out)
     for (size_t i = 0; i < n; ++i) tickets_out[i] = tk[i];
   return MS_OK;
