@@ -672,7 +672,8 @@ def run_serving(args, ms, torch):
         log("serving %s" % name)
         dst.zero_()
         before = e.stats()
-        res, lat = serving.run(e, lay, ks, src, dst, mode)
+        res, lat = serving.run(e, lay, ks, src, dst, mode,
+                               submit_threads=args.serving_threads)
         r = serving.summarize(res)
         after = e.stats()
         if mode == ms.MS_SERVE_BATCHED and name == "served_launch_stage":
@@ -716,7 +717,8 @@ def run_serving(args, ms, torch):
                 ("resident", ms.MS_SERVE_RESIDENT, eng, ks)):
             log("sweep %s %d req/s" % (name, rate))
             before = e.stats()
-            res, _ = serving.run(e, ls, kk, src, dst, mode)
+            res, _ = serving.run(e, ls, kk, src, dst, mode,
+                                 submit_threads=args.serving_threads)
             after = e.stats()
             row[name + "_GBps"] = round(res.data_gbps, 2)
             row[name + "_p50_us"] = round(res.p50_us, 1)
@@ -957,6 +959,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-duration", type=float, default=10.0)
+    ap.add_argument("--serving-threads", type=int, default=8,
+                    help="client threads that submit in the batched and "
+                         "resident serving modes")
     ap.add_argument("--serving-pool-pages", type=int, default=2097152)
     ap.add_argument("--sweep-rates", type=float, nargs="*",
                     default=[20000, 50000, 100000, 200000, 400000, 600000])
