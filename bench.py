@@ -295,39 +295,88 @@ def run_variants(args, ms, torch, b):
 
 
 def run_batched(args, ms, torch):
-    """Fused batched launch (graph replay) vs 512 plain launches."""
+    """Fused batched launch vs 512 plain launches.  The fused batch is timed
+    both ways ms_process_batch can issue it, graph replay and direct
+    launches, with the same tuning, in alternating blocks of 5 so that a
+    drift of the clock touches both alike; the 512 plain launches are
+    timed by the host clock (their cost is the host's launch path)."""
     import numpy as np
     from paper_2004_09252_amd import workloads
     w = workloads.batched(seed=3, with_data=False)
     total = w.total_pages
-    eng = ms.Engine(0)
-    keys = [eng.key_load(k) for k in w.keys]
+    engs = {"graph": ms.Engine(0, use_graphs=1),
+            "direct": ms.Engine(0, use_graphs=0)}
     buf = torch.randint(0, 256, (total * 4096,), dtype=torch.uint8,
                         device="cuda",
                         generator=torch.Generator("cuda").manual_seed(3))
     out = torch.empty_like(buf)
-    reqs = []
-    off = 0
-    for r in w.requests:
-        reqs.append(ms.request(keys[r.client], buf, out, r.n_pages,
-                               ms.linear_nonce(r.va, 4096, r.pid), op=r.op,
-                               client=r.client, src_offset_pages=off,
-                               dst_offset_pages=off))
-        off += r.n_pages
-    arr = (ms.ms_request * len(reqs))(*reqs)
-    tune = eng.autotune(total)
+    arrs, keys = {}, {}
+    for name, eng in engs.items():
+        keys[name] = [eng.key_load(k) for k in w.keys]
+        reqs = []
+        off = 0
+        for r in w.requests:
+            reqs.append(ms.request(keys[name][r.client], buf, out, r.n_pages,
+                                   ms.linear_nonce(r.va, 4096, r.pid),
+                                   op=r.op, client=r.client,
+                                   src_offset_pages=off,
+                                   dst_offset_pages=off))
+            off += r.n_pages
+        arrs[name] = (ms.ms_request * len(reqs))(*reqs)
+    default = "graph" if ms.ms_config_default().use_graphs else "direct"
+    tune = engs[default].autotune(total)
+    for name, eng in engs.items():
+        if name != default:
+            st = ms.ms_set_tuning(eng.ctx, tune)
+            if st:
+                raise RuntimeError(ms.ms_status_str(st))
     stream = torch.cuda.current_stream()
-    for _ in range(3):
-        eng.process_batch(arr, stream=stream)
+    fused = {}
+    for name, eng in engs.items():
+        for _ in range(3):
+            eng.process_batch(arrs[name], stream=stream)
+        torch.cuda.synchronize()
+        fused[name] = out.clone()
+        out.zero_()
+    # Device time of the fused batches, in alternating blocks: events go
+    # between the blocks on the one stream, with no host synchronisation
+    # until the end, so the host (about 0.2 ms per 512-request call) keeps
+    # ahead of the device and only the batches' own work and the gaps
+    # between them are timed.
+    # The checks above leave the device idle for some milliseconds, and
+    # the chip comes back from idle at a lower clock: batches run without
+    # a break for a while (args.ramp_seconds, at most 0.25 s) first.
+    reps = max(20, args.steps)
+    block = 5
+    n_blocks = (reps + block - 1) // block
+    ramp_end = time.perf_counter() + min(args.ramp_seconds, 0.25)
+    ramp_batches = 0
+    while True:
+        engs[default].process_batch(arrs[default], stream=stream)
+        ramp_batches += 1
+        if time.perf_counter() >= ramp_end:
+            break
+    e_start = torch.cuda.Event(enable_timing=True)
+    e_start.record(stream)
+    marks = []
+    for _ in range(n_blocks):
+        for name, eng in engs.items():
+            for _ in range(block):
+                eng.process_batch(arrs[name], stream=stream)
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            marks.append((name, e))
     torch.cuda.synchronize()
-    reps = max(5, args.steps // 4)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        eng.process_batch(arr, stream=stream)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / reps
-    fused = out.clone()
+    t_fused = {name: 0.0 for name in engs}
+    prev = e_start
+    for name, e in marks:
+        t_fused[name] += prev.elapsed_time(e) * 1e-3
+        prev = e
+    n_fused = block * n_blocks
+    t_fused = {k: v / n_fused for k, v in t_fused.items()}
     out.zero_()
+    eng = engs[default]
+    reqs = list(arrs[default])
 
     def plain_all():
         for r in reqs:
@@ -342,15 +391,24 @@ def run_batched(args, ms, torch):
         plain_all()
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / reps
-    same = bool(torch.equal(fused, out))
-    for k in keys:
-        eng.key_destroy(k)
-    eng.close()
+    same = all(bool(torch.equal(f, out)) for f in fused.values())
+    for name, e in engs.items():
+        for k in keys[name]:
+            e.key_destroy(k)
+        e.close()
+    gbps = {k: round(total * 4096 / v / 1e9, 2) for k, v in t_fused.items()}
     return {"requests": len(reqs), "pages": int(total),
-            "fused_graph_GBps": round(total * 4096 / t_batch / 1e9, 2),
+            "fused_GBps": gbps[default],
+            "fused_graph_GBps": gbps["graph"],
+            "fused_direct_GBps": gbps["direct"],
             "plain_launches_GBps": round(total * 4096 / t_plain / 1e9, 2),
-            "fused_ms": round(t_batch * 1e3, 4),
+            "fused_ms": round(t_fused[default] * 1e3, 4),
+            "fused_graph_ms": round(t_fused["graph"] * 1e3, 4),
+            "fused_direct_ms": round(t_fused["direct"] * 1e3, 4),
             "plain_ms": round(t_plain * 1e3, 4),
+            "fused_reps": n_fused,
+            "ramp_batches": ramp_batches,
+            "default_launch": default,
             "fused_equals_plain": same,
             "tuning": {"pages_per_wave": tune.pages_per_wave,
                        "unroll": tune.unroll,

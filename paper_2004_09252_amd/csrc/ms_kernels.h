@@ -75,6 +75,14 @@ hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
 const void* batch_kernel_fn(uint32_t unroll, uint32_t cipher, int rounds);
 const void* plain_kernel_fn(uint32_t unroll, uint32_t cipher, int rounds,
                             uint32_t kind);
+// Copies a batch buffer of `bytes` (a multiple of 16) from pinned host
+// memory `host` to device memory `dev` with a kernel on `stream` (see
+// desc_copy_kernel); desc_copy_fn and desc_copy_blocks give its entry point
+// and grid for graph kernel nodes (arguments: dev, host, bytes / 16).
+hipError_t launch_desc_copy(void* dev, const void* host, size_t bytes,
+                            hipStream_t stream);
+const void* desc_copy_fn();
+uint32_t desc_copy_blocks(size_t bytes);
 // A plain launch covers at most this many pages (32-bit page counters in
 // the kernel); longer runs are split into several launches.
 constexpr uint64_t kMaxPagesPerPlainLaunch = 1ull << 24;

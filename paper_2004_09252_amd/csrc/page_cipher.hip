@@ -295,6 +295,25 @@ __global__ __launch_bounds__(kBlockThreads) void fill_u32_kernel(
     dst[i] = value;
 }
 
+// A batch's request records, from the pinned host staging buffer into the
+// device array the batch kernel reads.  It runs on the batch's own queue, so
+// the batch kernel waits for it by queue order alone; a copy-engine transfer
+// would add a wait across engines before and after it.  The loads are
+// system-scope, so they read what the host wrote before the launch.
+__global__ __launch_bounds__(kBlockThreads) void desc_copy_kernel(
+    uint4* __restrict__ dst, const uint64_t* __restrict__ src, uint32_t n16) {
+  const uint32_t i = blockIdx.x * kBlockThreads + threadIdx.x;
+  if (i >= n16) return;
+  const uint64_t lo =
+      __hip_atomic_load(src + 2u * i, __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_SYSTEM);
+  const uint64_t hi =
+      __hip_atomic_load(src + 2u * i + 1u, __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_SYSTEM);
+  dst[i] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi,
+                      (uint32_t)(hi >> 32));
+}
+
 // Plain kernel for one (cipher, rounds, unroll, nonce kind).
 template <uint32_t CIPHER, int ROUNDS, int UNROLL>
 const void* plain_fn(uint32_t kind) {
@@ -406,6 +425,28 @@ hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
   void* args[] = {(void*)&batch, (void*)&keys, (void*)&pages_per_wave};
   return hipLaunchKernel(fn, dim3(grid_blocks), dim3(kBlockThreads), args, 0,
                          stream);
+}
+
+const void* desc_copy_fn() {
+  return reinterpret_cast<const void*>(&desc_copy_kernel);
+}
+
+uint32_t desc_copy_blocks(size_t bytes) {
+  const size_t n16 = bytes / 16;
+  return (uint32_t)((n16 + kBlockThreads - 1) / kBlockThreads);
+}
+
+hipError_t launch_desc_copy(void* dev, const void* host, size_t bytes,
+                            hipStream_t stream) {
+  if (!dev || !host || bytes == 0 || bytes % 16 != 0 ||
+      bytes / 16 > 0xffffffffull)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(desc_copy_kernel, dim3(desc_copy_blocks(bytes)),
+                     dim3(kBlockThreads), 0, stream,
+                     reinterpret_cast<uint4*>(dev),
+                     reinterpret_cast<const uint64_t*>(host),
+                     (uint32_t)(bytes / 16));
+  return hipGetLastError();
 }
 
 // Request descriptors of ms_process_batch_static.  Host code must not pass

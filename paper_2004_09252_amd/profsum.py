@@ -14,7 +14,9 @@ Usage (from the repository root, on the databases a profiling run left):
 
 ``trace`` writes the kernel-trace statistics (rocprofv3 --kernel-trace
 --stats): per kernel and grid size, the number of dispatches and their
-average, minimum and maximum duration.
+average, minimum and maximum duration; where fused batch launches were
+traced, also the parts of one launch (descriptor copy, batch kernel and the
+gaps before each).
 
 ``resident`` summarises one run of the resident-key kernel on HBM pages
 (bench.py --resident-device-only): its dispatch duration, HBM bytes per page
@@ -87,8 +89,54 @@ def trace(db_path: str, out_path: str, cmd: str,
             "from top_kernels limit 12"):
         lines.append("| %s | %d | %.2f | %.2f | %.1f |" % (
             _short(name), calls, total / 1e3, avg, pct))
+    lines += _batch_launch_lines(db)
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
+
+
+DESC_COPY_KERNEL = "desc_copy_kernel"
+BATCH_KERNEL = "batch_pages_kernel"
+
+
+def _batch_launch_lines(db) -> list:
+    """Fused batch launches (descriptor copy kernel, then the batch kernel
+    on the same queue): the gap from the queue's previous kernel to the
+    copy, the copy, the gap from the copy to the batch kernel, and the batch
+    kernel, as median / 10th / 90th percentile over the launches traced,
+    per hardware queue (graph replays and direct launches may run on
+    different queues)."""
+    ks = list(db.execute("select name, queue_id, start, end from kernels "
+                         "order by start"))
+    by_q = collections.defaultdict(list)
+    for k in ks:
+        by_q[k[1]].append(k)
+    names = ("previous kernel -> copy", "descriptor copy",
+             "copy -> batch kernel", "batch kernel")
+    per_q = {}
+    for qid, q in sorted(by_q.items()):
+        parts = collections.defaultdict(list)
+        for i in range(1, len(q) - 1):
+            if DESC_COPY_KERNEL in q[i][0] and BATCH_KERNEL in q[i + 1][0]:
+                parts[names[0]].append(q[i][2] - q[i - 1][3])
+                parts[names[1]].append(q[i][3] - q[i][2])
+                parts[names[2]].append(q[i + 1][2] - q[i][3])
+                parts[names[3]].append(q[i + 1][3] - q[i + 1][2])
+        if parts:
+            per_q[qid] = parts
+    if not per_q:
+        return []
+    out = ["", "Fused batch launches (descriptor copy kernel, then the batch "
+           "kernel, on one queue); microseconds:", "",
+           "| queue | launches | part | median | p10 | p90 |",
+           "|---|---|---|---|---|---|"]
+    for qid, parts in per_q.items():
+        n = len(parts[names[3]])
+        for name in names:
+            v = sorted(parts[name])
+            out.append("| %s | %d | %s | %.1f | %.1f | %.1f |" % (
+                qid, n, name, v[len(v) // 2] / 1e3, v[len(v) // 10] / 1e3,
+                v[(9 * len(v)) // 10] / 1e3))
+    return out
 
 
 def _counter(db_path: str, counter: str):

@@ -140,6 +140,8 @@ hipError_t hipGraphAddKernelNode(hipGraphNode_t* n, hipGraph_t g,
 hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, void* err,
                                char* log, size_t log_size);
 hipError_t hipGraphExecDestroy(hipGraphExec_t e);
+hipError_t hipGraphExecKernelNodeSetParams(hipGraphExec_t e, hipGraphNode_t n,
+                                           const hipKernelNodeParams* p);
 hipError_t hipGraphExecMemcpyNodeSetParams1D(hipGraphExec_t e,
                                              hipGraphNode_t n, void* dst,
                                              const void* src, size_t count,

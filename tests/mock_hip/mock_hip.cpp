@@ -301,6 +301,9 @@ hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
 // batch as the kernel node of a graph would.
 void mock_run_batch_node(const void* func, const void* hdr,
                          const uint32_t* keys, uint32_t ppw);
+namespace ms {
+const void* desc_copy_fn();   // mock_kernels.cpp
+}
 
 struct MockGraphNode {
   int kind = 0;  // 0 memcpy, 1 kernel
@@ -342,12 +345,27 @@ hipError_t hipGraphAddMemcpyNode1D(hipGraphNode_t* n, hipGraph_t g,
   *n = node;
   return hipSuccess;
 }
+// The kernels a graph captures: the descriptor copy (dst, src, 16-byte
+// units), run as a memmove, and the fused batch kernel (header, key table,
+// pages per wave); arguments are taken by value as the runtime does.
+bool mock_copy_node_params(const hipKernelNodeParams* p, MockGraphNode* node) {
+  if (p->func != ms::desc_copy_fn()) return false;
+  node->kind = 0;
+  node->dst = *static_cast<void* const*>(p->kernelParams[0]);
+  node->src = *static_cast<const void* const*>(p->kernelParams[1]);
+  node->count = (size_t)*static_cast<const uint32_t*>(p->kernelParams[2]) * 16;
+  return true;
+}
+
 hipError_t hipGraphAddKernelNode(hipGraphNode_t* n, hipGraph_t g,
                                  const hipGraphNode_t*, size_t,
                                  const hipKernelNodeParams* p) {
-  // the only kernel captured is the fused batch kernel: (header, key
-  // table, pages per wave), taken by value as the runtime does
   auto* node = new MockGraphNode();
+  if (mock_copy_node_params(p, node)) {
+    g->nodes.push_back(node);
+    *n = node;
+    return hipSuccess;
+  }
   node->kind = 1;
   node->func = p->func;
   node->hdr = *static_cast<const void* const*>(p->kernelParams[0]);
@@ -378,6 +396,18 @@ hipError_t hipGraphExecMemcpyNodeSetParams1D(hipGraphExec_t e,
       e->nodes[i].dst = dst;
       e->nodes[i].src = src;
       e->nodes[i].count = count;
+      return hipSuccess;
+    }
+  return hipErrorInvalidValue;
+}
+hipError_t hipGraphExecKernelNodeSetParams(hipGraphExec_t e, hipGraphNode_t n,
+                                           const hipKernelNodeParams* p) {
+  for (size_t i = 0; i < e->orig.size(); ++i)
+    if (e->orig[i] == n) {
+      MockGraphNode x;
+      if (!mock_copy_node_params(p, &x) || e->nodes[i].kind != 0)
+        return hipErrorInvalidValue;   // only the copy node is updated
+      e->nodes[i] = x;
       return hipSuccess;
     }
   return hipErrorInvalidValue;

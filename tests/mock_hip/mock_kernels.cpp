@@ -148,6 +148,21 @@ hipError_t static_batch_scratch(void** out) {
   return hipSuccess;
 }
 
+// The descriptor copy: a stream-ordered memmove here (graph nodes of it are
+// recognised by this entry point in mock_hip.cpp).
+static const char g_desc_copy = 0;
+const void* desc_copy_fn() { return &g_desc_copy; }
+uint32_t desc_copy_blocks(size_t bytes) {
+  return (uint32_t)((bytes / 16 + kBlockThreads - 1) / kBlockThreads);
+}
+hipError_t launch_desc_copy(void* dev, const void* host, size_t bytes,
+                            hipStream_t stream) {
+  if (!dev || !host || bytes == 0 || bytes % 16 != 0)
+    return hipErrorInvalidValue;
+  mock_enqueue(stream, [dev, host, bytes] { std::memmove(dev, host, bytes); });
+  return hipSuccess;
+}
+
 hipError_t launch_copy(const void*, void*, uint64_t, uint32_t, hipStream_t) {
   return hipErrorInvalidValue;
 }

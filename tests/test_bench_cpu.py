@@ -115,3 +115,40 @@ def test_resident_summary_arithmetic(tmp_path):
     assert float(vals["dispatch_duration_ms"]) == pytest.approx(2.5)
     assert vals["workgroups_x_threads"] == "256 x 256"
     assert float(vals["grbm_gui_active_cycles_per_xcd"]) == pytest.approx(100)
+
+
+def test_batch_launch_parts_from_a_trace():
+    """profsum's breakdown of fused batch launches: per queue, each
+    descriptor copy directly followed by a batch kernel gives the gap
+    before the copy, the copy, the gap to the batch kernel and the batch
+    kernel; a copy followed by anything else does not count, and each
+    queue gets rows of its own."""
+    from paper_2004_09252_amd import profsum
+    db = sqlite3.connect(":memory:")
+    db.execute("create table kernels (name text, queue_id int, start int, "
+               "end int)")
+    rows = [("plain_pages_kernel", 1, 0, 100_000)]
+    t = 100_000
+    for i in range(5):   # gaps 10 us, copy 4 us, 0 us, batch 400 us
+        rows.append(("ms::desc_copy_kernel(a)", 1, t + 10_000, t + 14_000))
+        rows.append(("void ms::batch_pages_kernel<0u, 20, 1>(x)", 1,
+                     t + 14_000, t + 414_000))
+        t += 414_000
+    # a copy with no batch kernel after it, and a pair on another queue
+    rows.append(("ms::desc_copy_kernel(a)", 1, t + 1000, t + 2000))
+    rows.append(("plain_pages_kernel", 1, t + 3000, t + 4000))
+    rows.append(("other", 2, 0, 1))
+    rows.append(("ms::desc_copy_kernel(a)", 2, 5, 6))
+    rows.append(("void ms::batch_pages_kernel<0u, 20, 1>(x)", 2, 8, 9))
+    db.executemany("insert into kernels values (?, ?, ?, ?)", rows)
+    lines = profsum._batch_launch_lines(db)
+    rows = [l.split(" | ") for l in lines if l.startswith("| 1 ")]
+    table = {r[2]: tuple(float(x.strip(" |")) for x in r[3:]) for r in rows}
+    assert all(r[1] == "5" for r in rows), rows
+    assert table["previous kernel -> copy"] == (10.0, 10.0, 10.0)
+    assert table["descriptor copy"] == (4.0, 4.0, 4.0)
+    assert table["copy -> batch kernel"] == (0.0, 0.0, 0.0)
+    assert table["batch kernel"] == (400.0, 400.0, 400.0)
+    # queue 2's pair is reported on its own rows
+    q2 = [l for l in lines if l.startswith("| 2 | 1 | ")]
+    assert len(q2) == 4, lines
