@@ -167,6 +167,42 @@ def test_graph_replays_with_eager_work_between(ms, eng):
         eng.key_destroy(k)
 
 
+def test_batches_of_changing_size_reuse_every_buffer(ms):
+    """Calls of 1024, 3 and 200 requests in an order that reuses each of
+    the context's batch buffers with a different size, so the descriptor
+    copy (a graph node, or a direct launch) changes size and grid from call
+    to call: every call's output equals the oracle, request by request, in
+    both launch forms."""
+    import torch
+    sizes = [1024, 3, 200, 3, 1024, 200, 3, 1024, 200]
+    ws = {n: _small(60 + n % 7, n_requests=n, max_pages=3)
+          for n in sorted(set(sizes))}
+    want = {n: np.concatenate([x.reshape(-1) for x in
+                               _expected(w, w.plain, _linear_nonces(w))])
+            for n, w in ws.items()}
+    stream = torch.cuda.current_stream()
+    for use_graphs in (1, 0):
+        _note("changing batch sizes, use_graphs=%d" % use_graphs)
+        e = ms.Engine(0, use_graphs=use_graphs)
+        try:
+            data = {}
+            for n, w in ws.items():
+                keys = [e.key_load(k) for k in w.keys]
+                flat = np.concatenate([x.reshape(-1) for x in w.plain])
+                src = torch.from_numpy(flat).to("cuda")
+                dst = torch.zeros_like(src)
+                data[n] = (src, dst, _layout(ms, e, w, keys, src, dst))
+            for i, n in enumerate(sizes):
+                src, dst, arr = data[n]
+                dst.fill_(i + 1)
+                e.process_batch(arr, stream=stream)
+                torch.cuda.synchronize()
+                assert np.array_equal(dst.cpu().numpy(), want[n]), \
+                    (use_graphs, i, n)
+        finally:
+            e.close()
+
+
 def test_batched_mixed_nonce_kinds_empty_and_in_place(ms, eng):
     _note("mixed nonce kinds, empty requests, in place")
     import torch
