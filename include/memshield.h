@@ -280,9 +280,11 @@ ms_status ms_plain_launch_info(ms_ctx *ctx, uint64_t n_pages,
 
 /*
  * Run n requests, each with its own key, nonce and page count, as ONE fused
- * persistent launch enqueued on `stream` (a replay of a captured hipGraph when
- * use_graphs is on), using the tuning that ms_autotune picked for a batch of
- * this size (or the built-in default).  Requests with n_pages == 0 are
+ * persistent launch enqueued on `stream`, using the tuning that ms_autotune
+ * picked for a batch of this size (or the built-in default).  The request
+ * descriptors go from a pinned host buffer of the context to device memory
+ * through a small copy kernel on the same stream, ahead of the batch kernel;
+ * with use_graphs on, the two are one replay of a captured hipGraph.  Requests with n_pages == 0 are
  * skipped.  Destinations must not overlap each other or any source other
  * than their own.  Returns once enqueued; the request array may be reused at
  * once.  At most max_batch_requests requests.  Errors: MS_EINVAL, MS_ENOKEY,
@@ -299,8 +301,7 @@ ms_status ms_process_batch(ms_ctx *ctx, const ms_request *reqs, size_t n,
  * bytes per request) go to a device array of fixed size built into the
  * library, one per GPU, held until the process ends, through a pinned host
  * buffer that ms_init allocated; the kernel is launched directly (no graph)
- * on `stream` after a host-to-device copy of the descriptors on the same
- * stream.  At most MS_STATIC_BATCH_MAX_REQUESTS requests (256 KiB of
+ * on `stream` after the descriptor copy kernel on the same stream.  At most MS_STATIC_BATCH_MAX_REQUESTS requests (256 KiB of
  * descriptors), else MS_EINVAL.  Before it reuses the host buffer, a call
  * waits on the host until the previous call's copy and kernel are done.
  * Calls on one GPU share the device array: calls on different streams that
