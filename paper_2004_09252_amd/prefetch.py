@@ -106,7 +106,9 @@ class PagedMemory:
         self.hints_issued = 0
         self.hints_dropped = 0
         self.hint_waits = 0
-        self.flush_events = []      # (start, end) events of each launch
+        # (start, end) events around each ms_process_batch call: the
+        # interval includes the call's host-side preparation
+        self.flush_events = []
         self.time_flushes = False
         self._reset_queue()
 
