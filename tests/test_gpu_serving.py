@@ -600,3 +600,38 @@ def test_engine_holds_tensors_of_requests_in_flight(ms, stage):
         assert all(w() is None for w in refs)
     finally:
         eng.close()
+
+
+def test_ring_stage_size_boundary(ms):
+    """On the ring stage, requests of 1, 1023 and 1024 pages (the ring's
+    limit) go to the ring and one of 1025 pages to a fused launch; all of
+    them, submitted in one call, equal the oracle page for page, and the
+    context's counters place each where its size says."""
+    _note("ring stage size boundary: 1, 1023, 1024, 1025 pages")
+    import torch
+    eng = ms.Engine(0, serve_stage=ms.MS_SERVE_STAGE_RING)
+    try:
+        r = _Reqs(ms, eng, seed=50, n=4, max_pages=2)
+        r.pages[:] = [1, 1023, 1024, 1025]
+        r.off = np.concatenate([[0], np.cumsum(r.pages)[:-1]])
+        rng = np.random.default_rng(51)
+        total = int(r.pages.sum())
+        r.host = workloads.random_pages(rng, total).reshape(-1)
+        r.src = torch.from_numpy(r.host).to("cuda")
+        r.dst_a = torch.zeros_like(r.src)
+        torch.cuda.synchronize()
+        t0 = eng.submit([r.req(0, r.dst_a)])       # the ring is up
+        assert eng.poll(t0, timeout_s=30)[0] == 0
+        before = eng.stats()
+        t = eng.submit([r.req(i, r.dst_a) for i in range(4)])
+        st, done = eng.poll(t, timeout_s=60)
+        assert st == 0 and done == [1, 1, 1, 1]
+        after = eng.stats()
+        on_ring = ((after.ring_direct - before.ring_direct) +
+                   (after.ring_queued - before.ring_queued))
+        assert on_ring == 3, on_ring
+        assert after.batches - before.batches == 1
+        for i in range(4):
+            assert np.array_equal(r.slice(r.dst_a, i), r.expect(i)), i
+    finally:
+        eng.close()
