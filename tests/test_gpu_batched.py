@@ -312,3 +312,47 @@ def test_batched_salsa20_per_request(ms, rounds):
             e.key_destroy(k)
     finally:
         e.close()
+
+
+def test_static_batch_at_its_request_limit(ms):
+    """ms_process_batch_static with MS_STATIC_BATCH_MAX_REQUESTS one-page
+    requests (the largest descriptor array, so the largest descriptor copy)
+    equals the oracle page for page; one request more is MS_EINVAL and
+    writes nothing."""
+    _note("static batch at its limit")
+    import torch
+    n = ms.MS_STATIC_BATCH_MAX_REQUESTS
+    rng = np.random.default_rng(52)
+    kb = [rng.bytes(32) for _ in range(3)]
+    e = ms.Engine(0)
+    try:
+        keys = [e.key_load(k) for k in kb]
+        host = workloads.random_pages(rng, n + 1)
+        src = torch.from_numpy(host.reshape(-1).copy()).to("cuda")
+        dst = torch.zeros_like(src)
+        kidx = rng.integers(0, 3, size=n + 1)
+        va = 0x7F0000000000 + 4096 * rng.integers(0, 1 << 24, size=n + 1)
+        reqs = [ms.request(keys[int(kidx[i])], src, dst, 1,
+                           ms.linear_nonce(int(va[i]), 4096, 2000 + i),
+                           client=int(kidx[i]), src_offset_pages=i,
+                           dst_offset_pages=i) for i in range(n + 1)]
+        over = (ms.ms_request * (n + 1))(*reqs)
+        assert ms.ms_process_batch_static(e.ctx, over) == ms.MS_EINVAL
+        torch.cuda.synchronize()
+        assert int(dst.count_nonzero()) == 0
+        e.process_batch_static((ms.ms_request * n)(*reqs[:n]),
+                               stream=torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        got = dst.cpu().numpy().reshape(n + 1, 4096)
+        nonces = np.empty((n, 12), np.uint8)
+        nonces[:, 0:8] = va[:n].astype("<u8").view(np.uint8).reshape(n, 8)
+        nonces[:, 8:12] = (2000 + np.arange(n)).astype("<u4").view(
+            np.uint8).reshape(n, 4)
+        for k in range(3):
+            sel = np.nonzero(kidx[:n] == k)[0]
+            want = oracle.cipher_pages(kb[k], nonces[sel], host[sel],
+                                       threads=HOST_THREADS)
+            assert np.array_equal(got[sel], want), k
+        assert not got[n].any()
+    finally:
+        e.close()
