@@ -909,6 +909,23 @@ bool launch_one(ms_ctx* c) {
     if (hip_ok(e)) e = hipEventRecord(s.done, strm);
     if (!hip_ok(e)) st = dev_err(c, e);
     s.used = true;
+  } else if (copy && take.size() <= ms::kInlineBatchMax) {
+    // a small batch: its records go in the kernel arguments, so no
+    // descriptor copy runs (and waits for this thread's second launch call)
+    // ahead of the batch kernel
+    ms::InlineBatch ib;
+    uint64_t tot = 0;
+    fill_descriptors(
+        reinterpret_cast<uint8_t*>(&ib),
+        [&rp](size_t i) -> const ms_request& { return *rp[i]; }, ks.data(),
+        take.size(), &tot);
+    const Tuning t = tuning_for(c, total);
+    hipError_t e = ms::launch_batch_inline(
+        ib, c->d_keys, t.ppw, t.unroll, grid_blocks_for(c, t, total),
+        c->cfg.cipher, (int)c->cfg.rounds, strm);
+    if (hip_ok(e)) e = hipEventRecord(s.done, strm);
+    if (!hip_ok(e)) st = dev_err(c, e);
+    s.used = true;
   } else if (copy) {
     st = issue_slot(c, s, copy, total, strm, false);
   } else if (!hip_ok(hipEventRecord(s.done, strm))) {

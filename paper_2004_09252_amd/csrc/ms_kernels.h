@@ -44,6 +44,16 @@ struct DevBatchHdr {
 };
 static_assert(sizeof(DevBatchHdr) == 64, "DevBatchHdr layout");
 
+// A batch of at most kInlineBatchMax requests whose header and records
+// travel in the kernel arguments (no descriptor copy before the launch).
+constexpr uint32_t kInlineBatchMax = 15;
+struct InlineBatch {
+  DevBatchHdr hdr;
+  DevReq req[kInlineBatchMax];
+};
+static_assert(sizeof(InlineBatch) == 64 * (1 + kInlineBatchMax),
+              "InlineBatch layout");
+
 // Arguments of one plain launch over a run of pages.
 struct PlainArgs {
   const uint32_t* keys;  // device key table, 8 words per slot
@@ -70,6 +80,11 @@ hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
                         uint32_t pages_per_wave, uint32_t unroll,
                         uint32_t grid_blocks, uint32_t cipher, int rounds,
                         hipStream_t stream);
+// The fused batch kernel reading its records from the kernel arguments.
+hipError_t launch_batch_inline(const InlineBatch& batch, const uint32_t* keys,
+                               uint32_t pages_per_wave, uint32_t unroll,
+                               uint32_t grid_blocks, uint32_t cipher,
+                               int rounds, hipStream_t stream);
 // Kernel entry points (graph capture, occupancy queries); nullptr for a
 // combination that does not exist.
 const void* batch_kernel_fn(uint32_t unroll, uint32_t cipher, int rounds);

@@ -236,6 +236,25 @@ __global__ __launch_bounds__(kBlockThreads, UNROLL == 2 ? 7 : 8) void batch_page
       lds[w], w);
 }
 
+// The same batch with its header and records in the kernel arguments (a
+// batch of at most kInlineBatchMax requests), so that no descriptor copy has
+// to run before it.  They are read where the dispatch placed the arguments,
+// through the kernarg segment pointer, with scalar loads like the device
+// array of the kernel above.
+template <uint32_t CIPHER, int ROUNDS, int UNROLL>
+__global__ __launch_bounds__(kBlockThreads, UNROLL == 2 ? 7 : 8) void batch_inline_kernel(
+    InlineBatch batch, const uint32_t* __restrict__ keys,
+    uint32_t pages_per_wave) {
+  (void)batch;
+  __shared__ uint4 lds[kWavesPerBlock][256];
+  const uint32_t w = wave_in_block();
+  const auto* kb = (const __attribute__((address_space(4))) InlineBatch*)
+      __builtin_amdgcn_kernarg_segment_ptr();
+  batch_body<CIPHER, ROUNDS, UNROLL>(
+      (const DevBatchHdr*)&kb->hdr, (const DevReq*)&kb->req[0], keys,
+      pages_per_wave, lds[w], w);
+}
+
 // --------------------------------------------------------------- probes ---
 
 // Streaming copy: one wave per 4 KiB page, coalesced non-temporal dwordx4
@@ -363,6 +382,27 @@ const void* batch_fn_c(uint32_t unroll, int rounds) {
   return nullptr;
 }
 
+template <uint32_t CIPHER>
+const void* batch_inline_fn_c(uint32_t unroll, int rounds) {
+#define MS_INLINE_FN(R, U) \
+  reinterpret_cast<const void*>(&batch_inline_kernel<CIPHER, R, U>)
+  if (unroll == 2) {
+    switch (rounds) {
+      case 20: return MS_INLINE_FN(20, 2);
+      case 12: return MS_INLINE_FN(12, 2);
+      case 8: return MS_INLINE_FN(8, 2);
+    }
+  } else if (unroll == 1) {
+    switch (rounds) {
+      case 20: return MS_INLINE_FN(20, 1);
+      case 12: return MS_INLINE_FN(12, 1);
+      case 8: return MS_INLINE_FN(8, 1);
+    }
+  }
+#undef MS_INLINE_FN
+  return nullptr;
+}
+
 }  // namespace
 
 const void* plain_kernel_fn(uint32_t unroll, uint32_t cipher, int rounds,
@@ -380,6 +420,29 @@ const void* batch_kernel_fn(uint32_t unroll, uint32_t cipher, int rounds) {
     case kCipherSalsa: return batch_fn_c<kCipherSalsa>(unroll, rounds);
   }
   return nullptr;
+}
+
+hipError_t launch_batch_inline(const InlineBatch& batch, const uint32_t* keys,
+                               uint32_t pages_per_wave, uint32_t unroll,
+                               uint32_t grid_blocks, uint32_t cipher,
+                               int rounds, hipStream_t stream) {
+  const void* fn = nullptr;
+  switch (cipher) {
+    case kCipherChaCha:
+      fn = batch_inline_fn_c<kCipherChaCha>(unroll, rounds);
+      break;
+    case kCipherSalsa:
+      fn = batch_inline_fn_c<kCipherSalsa>(unroll, rounds);
+      break;
+  }
+  if (!fn || pages_per_wave == 0 || grid_blocks == 0 ||
+      batch.hdr.n_req == 0 || batch.hdr.n_req > kInlineBatchMax)
+    return hipErrorInvalidValue;
+  // the runtime copies the arguments at the launch
+  void* args[] = {const_cast<InlineBatch*>(&batch), (void*)&keys,
+                  (void*)&pages_per_wave};
+  return hipLaunchKernel(fn, dim3(grid_blocks), dim3(kBlockThreads), args, 0,
+                         stream);
 }
 
 hipError_t launch_plain(const PlainArgs& a, uint32_t kind, uint32_t cipher,

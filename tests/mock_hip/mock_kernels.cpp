@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <memory>
 
 #include "ms_internal.h"
 #include "ms_kernels.h"
@@ -134,6 +135,20 @@ hipError_t launch_batch(const DevBatchHdr* batch, const uint32_t* keys,
   if (grid_blocks == 0 || (unroll != 1 && unroll != 2)) return hipErrorInvalidValue;
   mock_enqueue(stream, [batch, keys, which, rounds] {
     run_batch(batch, keys, which, rounds);
+  });
+  return hipSuccess;
+}
+
+hipError_t launch_batch_inline(const InlineBatch& batch, const uint32_t* keys,
+                               uint32_t, uint32_t unroll, uint32_t grid_blocks,
+                               uint32_t which, int rounds, hipStream_t stream) {
+  if (grid_blocks == 0 || (unroll != 1 && unroll != 2) ||
+      batch.hdr.n_req == 0 || batch.hdr.n_req > kInlineBatchMax)
+    return hipErrorInvalidValue;
+  // the arguments are copied at the launch, as the runtime does
+  auto copy = std::make_shared<InlineBatch>(batch);
+  mock_enqueue(stream, [copy, keys, which, rounds] {
+    run_batch(&copy->hdr, keys, which, rounds);
   });
   return hipSuccess;
 }

@@ -635,3 +635,27 @@ def test_ring_stage_size_boundary(ms):
             assert np.array_equal(r.slice(r.dst_a, i), r.expect(i)), i
     finally:
         eng.close()
+
+
+@pytest.mark.parametrize("n", [2, 15, 16, 40])
+def test_launch_stage_one_batch_per_submission(ms, n):
+    """On the launch stage, one submission of n requests with nothing in
+    flight becomes one fused launch: up to 15 requests with their records
+    in the kernel arguments, more through the descriptor copy.  Every
+    request equals the oracle, and each submission counts one batch."""
+    _note("launch stage, one batch of %d requests" % n)
+    eng = ms.Engine(0, serve_stage=ms.MS_SERVE_STAGE_LAUNCH)
+    try:
+        r = _Reqs(ms, eng, seed=60 + n, n=n, max_pages=6)
+        for rep, dst in enumerate((r.dst_a, r.dst_b)):
+            eng.drain(timeout_s=30)
+            before = eng.stats()
+            t = eng.submit([r.req(i, dst) for i in range(n)])
+            st, done = eng.poll(t, timeout_s=30)
+            assert st == 0 and done == [1] * n
+            after = eng.stats()
+            assert after.batches - before.batches == 1, rep
+            for i in range(n):
+                assert np.array_equal(r.slice(dst, i), r.expect(i)), (rep, i)
+    finally:
+        eng.close()
