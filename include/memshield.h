@@ -119,9 +119,11 @@ typedef struct ms_config {
     uint32_t validate_pointers;   /* 1 (default): check every device range */
     uint32_t use_graphs;          /* 1 (default): ms_process_batch replays a
                                      captured hipGraph of its descriptor copy
-                                     and batch kernel; 0: it launches the
-                                     two directly (the serving scheduler
-                                     always does) */
+                                     and batch kernel; 0: it launches
+                                     directly, a batch of at most 15
+                                     requests as one kernel with its records
+                                     in the arguments (the serving
+                                     scheduler always launches directly) */
     uint32_t host_chunk_pages;    /* staged host-page calls: pages per chunk
                                      (default 16384, at most 65536) */
     uint32_t host_stage_slots;    /* staged host-page calls: device staging

@@ -718,7 +718,9 @@ ms_status get_graph(ms_ctx* c, BatchSlot& s, const Tuning& t, uint32_t grid,
   return MS_OK;
 }
 
-// Issue a filled slot on `stream`: graph replay or copy + launch.
+// Issue a filled slot on `stream`: graph replay, or direct launches (the
+// records in the kernel arguments for a batch of at most kInlineBatchMax
+// requests, else a descriptor copy and the batch kernel).
 ms_status issue_slot(ms_ctx* c, BatchSlot& s, size_t copy_bytes,
                      uint64_t total, hipStream_t stream, bool use_graph) {
   const Tuning t = tuning_for(c, total);
@@ -734,6 +736,15 @@ ms_status issue_slot(ms_ctx* c, BatchSlot& s, size_t copy_bytes,
     e = hipGraphExecKernelNodeSetParams(g->exec, g->copy, &cp);
     if (!hip_ok(e)) return dev_err(c, e);
     e = hipGraphLaunch(g->exec, stream);
+    if (!hip_ok(e)) return dev_err(c, e);
+  } else if (copy_bytes <= sizeof(ms::InlineBatch)) {
+    // a small batch: its records go in the kernel arguments, so no
+    // descriptor copy runs (and waits for this thread's second launch call)
+    // ahead of the batch kernel
+    ms::InlineBatch ib;
+    std::memcpy(&ib, s.host, copy_bytes);
+    e = ms::launch_batch_inline(ib, c->d_keys, t.ppw, t.unroll, grid,
+                                c->cfg.cipher, (int)c->cfg.rounds, stream);
     if (!hip_ok(e)) return dev_err(c, e);
   } else {
     e = ms::launch_desc_copy(s.dev, s.host, copy_bytes, stream);
@@ -906,23 +917,6 @@ bool launch_one(ms_ctx* c) {
         c->cfg.cipher, (int)c->cfg.rounds,
         (uint32_t)c->cu_count * t.waves_per_cu, t.unroll,
         strm);
-    if (hip_ok(e)) e = hipEventRecord(s.done, strm);
-    if (!hip_ok(e)) st = dev_err(c, e);
-    s.used = true;
-  } else if (copy && take.size() <= ms::kInlineBatchMax) {
-    // a small batch: its records go in the kernel arguments, so no
-    // descriptor copy runs (and waits for this thread's second launch call)
-    // ahead of the batch kernel
-    ms::InlineBatch ib;
-    uint64_t tot = 0;
-    fill_descriptors(
-        reinterpret_cast<uint8_t*>(&ib),
-        [&rp](size_t i) -> const ms_request& { return *rp[i]; }, ks.data(),
-        take.size(), &tot);
-    const Tuning t = tuning_for(c, total);
-    hipError_t e = ms::launch_batch_inline(
-        ib, c->d_keys, t.ppw, t.unroll, grid_blocks_for(c, t, total),
-        c->cfg.cipher, (int)c->cfg.rounds, strm);
     if (hip_ok(e)) e = hipEventRecord(s.done, strm);
     if (!hip_ok(e)) st = dev_err(c, e);
     s.used = true;
