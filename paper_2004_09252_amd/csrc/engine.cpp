@@ -354,11 +354,35 @@ ms_status check_sticky(ms_ctx* c) {
 }
 
 // A device range [p, p+bytes) must lie inside one device allocation.
+// Allocations a call has already found valid: the requests of one call
+// often share a buffer, and within a call the caller keeps every buffer
+// alive (the ABI's ownership rule), so a later range inside one of them
+// needs no runtime query.  Cleared by each call that uses it.
+struct RangeMemo {
+  static constexpr int kMax = 8;
+  uintptr_t base[kMax];
+  uint64_t size[kMax];
+  int n = 0;
+  bool covers(uintptr_t q, uint64_t bytes) const {
+    for (int i = 0; i < n; ++i)
+      if (q >= base[i] && bytes <= size[i] && q - base[i] <= size[i] - bytes)
+        return true;
+    return false;
+  }
+  void add(uintptr_t b, uint64_t sz) {
+    base[n % kMax] = b;
+    size[n % kMax] = sz;
+    n = n < kMax ? n + 1 : kMax;
+  }
+};
+
 ms_status check_device_range(ms_ctx* c, const void* p, uint64_t bytes,
-                             uint64_t align) {
+                             uint64_t align, RangeMemo* memo = nullptr) {
   if (!p) return MS_EINVAL;
   if (reinterpret_cast<uintptr_t>(p) % align) return MS_EINVAL;
   if (!c->cfg.validate_pointers) return MS_OK;
+  if (memo && memo->covers(reinterpret_cast<uintptr_t>(p), bytes))
+    return MS_OK;
   hipPointerAttribute_t attr;
   std::memset(&attr, 0, sizeof(attr));
   if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
@@ -377,6 +401,7 @@ ms_status check_device_range(ms_ctx* c, const void* p, uint64_t bytes,
   const uintptr_t b = reinterpret_cast<uintptr_t>(base);
   const uintptr_t q = reinterpret_cast<uintptr_t>(p);
   if (q < b || bytes > size || q - b > size - bytes) return MS_EINVAL;
+  if (memo) memo->add(b, size);
   return MS_OK;
 }
 
@@ -425,11 +450,12 @@ struct KeyPins {
   }
 };
 
-ms_status check_nonce(ms_ctx* c, const ms_nonce* n, uint64_t n_pages) {
+ms_status check_nonce(ms_ctx* c, const ms_nonce* n, uint64_t n_pages,
+                      RangeMemo* memo = nullptr) {
   if (!n) return MS_EINVAL;
   if (n->kind == MS_NONCE_ARRAY) {
     if (n_pages > (UINT64_MAX / 12)) return MS_EINVAL;
-    return check_device_range(c, n->array, n_pages * 12u, 4);
+    return check_device_range(c, n->array, n_pages * 12u, 4, memo);
   }
   if (n->kind == MS_NONCE_LINEAR) return MS_OK;
   return MS_EINVAL;
@@ -439,7 +465,8 @@ ms_status check_nonce(ms_ctx* c, const ms_nonce* n, uint64_t n_pages) {
 // `resolve` false the key handle is only decoded into its slot: the caller
 // checks it under the key lock itself.
 ms_status check_request(ms_ctx* c, const ms_request& r, uint32_t* slot,
-                        bool allow_empty, bool resolve = true) {
+                        bool allow_empty, bool resolve = true,
+                        RangeMemo* memo = nullptr) {
   if (r.priority != 0 || r.flags != 0) return MS_EINVAL;
   if (r.op != MS_ENCRYPT && r.op != MS_DECRYPT) return MS_EINVAL;
   if (r.n_pages == 0) {
@@ -447,15 +474,16 @@ ms_status check_request(ms_ctx* c, const ms_request& r, uint32_t* slot,
   } else {
     if (r.n_pages > (UINT64_MAX / MS_PAGE_SIZE)) return MS_EINVAL;
     const uint64_t bytes = r.n_pages * MS_PAGE_SIZE;
-    ms_status st = check_device_range(c, r.src, bytes, 16);
+    ms_status st = check_device_range(c, r.src, bytes, 16, memo);
     if (st) return st;
     // in place: the same range, already checked
-    if (r.dst != r.src && (st = check_device_range(c, r.dst, bytes, 16)))
+    if (r.dst != r.src &&
+        (st = check_device_range(c, r.dst, bytes, 16, memo)))
       return st;
     const uintptr_t s = reinterpret_cast<uintptr_t>(r.src);
     const uintptr_t d = reinterpret_cast<uintptr_t>(r.dst);
     if (s != d && ranges_overlap(s, bytes, d, bytes)) return MS_EINVAL;
-    st = check_nonce(c, &r.nonce, r.n_pages);
+    st = check_nonce(c, &r.nonce, r.n_pages, memo);
     if (st) return st;
   }
   if (!resolve) {
@@ -1231,9 +1259,10 @@ ms_status enqueue(ms_ctx* c, const ms_request* reqs, size_t n,
   thread_local std::vector<ms_ticket> tk;
   thread_local std::vector<Pending> direct, queued;
   ks.resize(n);
+  RangeMemo memo;
   for (size_t i = 0; i < n; ++i) {
     // the handle's liveness is checked below, with the reference taken
-    st = check_request(c, reqs[i], &ks[i], false, false);
+    st = check_request(c, reqs[i], &ks[i], false, false, &memo);
     if (st) return st;
     if (reqs[i].n_pages * MS_PAGE_SIZE > c->cfg.admission_cap_bytes)
       return MS_EINVAL;
@@ -1754,8 +1783,9 @@ ms_status ms_process_batch(ms_ctx* c, const ms_request* reqs, size_t n,
   if (!reqs || n > c->cfg.max_batch_requests) return MS_EINVAL;
   std::vector<uint32_t> ks(n);
   std::vector<const ms_request*> rp(n);
+  RangeMemo memo;
   for (size_t i = 0; i < n; ++i) {
-    st = check_request(c, reqs[i], &ks[i], true);
+    st = check_request(c, reqs[i], &ks[i], true, true, &memo);
     if (st) return st;
     rp[i] = &reqs[i];
   }
@@ -1790,8 +1820,10 @@ ms_status ms_process_batch_static(ms_ctx* c, const ms_request* reqs,
   // everything below uses storage sized at ms_init: no allocation
   std::lock_guard<std::mutex> lk(c->static_mu);
   uint32_t* ks = c->static_slots.data();
+  RangeMemo memo;
   for (size_t i = 0; i < n; ++i)
-    if ((st = check_request(c, reqs[i], &ks[i], true))) return st;
+    if ((st = check_request(c, reqs[i], &ks[i], true, true, &memo)))
+      return st;
   if ((st = check_batch_ranges(reqs, n, c->static_ranges))) return st;
   if ((st = pin_keys(c, &reqs[0].key, sizeof(ms_request), ks, n))) return st;
   KeyPins pins{c, ks, n};
