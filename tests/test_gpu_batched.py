@@ -356,3 +356,43 @@ def test_static_batch_at_its_request_limit(ms):
         assert not got[n].any()
     finally:
         e.close()
+
+
+def test_batch_validation_after_a_valid_request(ms, eng):
+    """A call remembers the allocations its earlier requests were checked
+    against; a later request that runs past the end of the same allocation,
+    or names host memory, is still refused (MS_EINVAL) by ms_process_batch
+    and by ms_submit, before anything runs."""
+    _note("batch validation after a valid request")
+    import torch
+    key = eng.key_generate()
+    n = 16384
+    # a fresh 64 MiB allocation that ends where the tensor ends (torch's
+    # cache could otherwise hand out the front of a larger one, and the
+    # check is against the runtime's allocation, not the tensor)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    buf = torch.zeros(n * 4096, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    p = buf.data_ptr()
+    seg = [s for s in torch.cuda.memory_snapshot()
+           if s["address"] <= p < s["address"] + s["total_size"]]
+    assert len(seg) == 1 and \
+        seg[0]["address"] + seg[0]["total_size"] == p + buf.numel(), seg
+    lin = ms.linear_nonce(0, 1, 0)
+    good = ms.request(key, buf, buf, 8, lin)
+    past_src = ms.request(key, buf, buf, 2, lin, src_offset_pages=n - 1,
+                          dst_offset_pages=100)
+    past_dst = ms.request(key, buf, buf, 2, lin, src_offset_pages=200,
+                          dst_offset_pages=n - 1)
+    host = np.zeros(3 * 4096 + 16, np.uint8)
+    hp = host.ctypes.data + (-host.ctypes.data) % 16
+    on_host = ms.ms_request(ms.MS_ENCRYPT, 0, key, hp, hp, 2, lin, 0, 0)
+    for bad in (past_src, past_dst, on_host):
+        for pair in ((good, bad), (bad, good)):
+            arr = (ms.ms_request * 2)(*pair)
+            assert ms.ms_process_batch(eng.ctx, arr) == ms.MS_EINVAL
+            assert ms.ms_submit(eng.ctx, arr)[0] == ms.MS_EINVAL
+    torch.cuda.synchronize()
+    assert int(buf.count_nonzero()) == 0
+    eng.key_destroy(key)
