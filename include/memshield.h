@@ -306,7 +306,9 @@ ms_status ms_process_batch(ms_ctx *ctx, const ms_request *reqs, size_t n,
  * bytes per request) go to a device array of fixed size built into the
  * library, one per GPU, held until the process ends, through a pinned host
  * buffer that ms_init allocated; the kernel is launched directly (no graph)
- * on `stream` after the descriptor copy kernel on the same stream.  At most MS_STATIC_BATCH_MAX_REQUESTS requests (256 KiB of
+ * on `stream` after the descriptor copy kernel on the same stream (a batch
+ * of at most 15 requests is one kernel with its records in the kernel
+ * arguments).  At most MS_STATIC_BATCH_MAX_REQUESTS requests (256 KiB of
  * descriptors), else MS_EINVAL.  Before it reuses the host buffer, a call
  * waits on the host until the previous call's copy and kernel are done.
  * Calls on one GPU share the device array: calls on different streams that

@@ -1839,12 +1839,20 @@ ms_status ms_process_batch_static(ms_ctx* c, const ms_request* reqs,
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   const Tuning t = tuning_for(c, total);
   const uint32_t grid = grid_blocks_for(c, t, total);
-  hipError_t e = ms::launch_desc_copy(c->d_static, c->h_static, copy, s);
-  if (hip_ok(e))
-    e = ms::launch_batch(static_cast<const ms::DevBatchHdr*>(c->d_static),
-                         c->d_keys, t.ppw, t.unroll, grid, c->cfg.cipher,
-                         (int)c->cfg.rounds,
-                         s);
+  hipError_t e;
+  if (copy <= sizeof(ms::InlineBatch)) {
+    // a small batch: one kernel, its records in the kernel arguments
+    ms::InlineBatch ib;
+    std::memcpy(&ib, c->h_static, copy);
+    e = ms::launch_batch_inline(ib, c->d_keys, t.ppw, t.unroll, grid,
+                                c->cfg.cipher, (int)c->cfg.rounds, s);
+  } else {
+    e = ms::launch_desc_copy(c->d_static, c->h_static, copy, s);
+    if (hip_ok(e))
+      e = ms::launch_batch(static_cast<const ms::DevBatchHdr*>(c->d_static),
+                           c->d_keys, t.ppw, t.unroll, grid, c->cfg.cipher,
+                           (int)c->cfg.rounds, s);
+  }
   if (hip_ok(e)) e = hipEventRecord(c->static_done, s);
   if (!hip_ok(e)) return dev_err(c, e);
   c->static_used = true;

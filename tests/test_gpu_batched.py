@@ -396,3 +396,29 @@ def test_batch_validation_after_a_valid_request(ms, eng):
     torch.cuda.synchronize()
     assert int(buf.count_nonzero()) == 0
     eng.key_destroy(key)
+
+
+def test_static_batch_small_calls(ms):
+    """ms_process_batch_static with 5 and then 15 requests (the most that
+    travel in the kernel arguments) and then 16 (through the device array):
+    each call equals the oracle, request by request."""
+    import torch
+    e = ms.Engine(0)
+    try:
+        for n in (5, 15, 16):
+            _note("static batch of %d requests" % n)
+            w = _small(70 + n, n_requests=n, max_pages=5)
+            keys = [e.key_load(k) for k in w.keys]
+            flat = np.concatenate([x.reshape(-1) for x in w.plain])
+            src = torch.from_numpy(flat).to("cuda")
+            dst = torch.zeros_like(src)
+            e.process_batch_static(_layout(ms, e, w, keys, src, dst),
+                                   stream=torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            want = np.concatenate([x.reshape(-1) for x in
+                                   _expected(w, w.plain, _linear_nonces(w))])
+            assert np.array_equal(dst.cpu().numpy(), want), n
+            for k in keys:
+                e.key_destroy(k)
+    finally:
+        e.close()
